@@ -1,0 +1,24 @@
+"""FP64 CPU oracle for the coverage-flow hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product package.  It shares no code
+with the HIP path (neither imports the other); the only common dependency is
+the seeded input generator module ``workloads``.
+
+Each function follows the paper's definitions directly, in float64:
+
+* ``sinkhorn``   - debiased Sinkhorn divergence, its gradient with respect to
+                   the trajectory samples and the reference weights
+                   (Sec. II-B, eqs. 5-7);
+* ``gmm_score``, ``median_bandwidth``, ``svgd_phi`` - the Stein variational
+                   flow with an RBF kernel and an analytic mixture score
+                   (Sec. II-B, eq. 4);
+* ``lqr_track_dense``, ``lqr_track_riccati`` - linear-quadratic flow matching
+                   (Sec. II-C, eqs. 8-10);
+* ``plan_step`` / ``plan`` - the outer planning loop (Sec. II-C).
+"""
+from .sinkhorn import sinkhorn, lse_update, gauge_fix, SinkhornResult  # noqa: F401
+from .svgd import gmm_score, gmm_logpdf, median_bandwidth, svgd_phi, pair_count  # noqa: F401
+from .lqr import lqr_track_dense, lqr_track_riccati  # noqa: F401
+from .plan import (dynamics_f, dynamics_jac, rollout, plan_step, plan,  # noqa: F401
+                   reference_flow)
