@@ -1,0 +1,276 @@
+/*
+ * ct.h - C ABI of the coverage-flow library (libct.so).
+ *
+ * The library evaluates the reference flow that pulls the T samples of a robot
+ * trajectory toward a target spatial distribution (Sun, Kwon, Murphey,
+ * "Scalable Coverage Trajectory Synthesis on GPUs as Statistical Inference",
+ * Sec. II), on one AMD MI355X (gfx950) with hand-written HIP kernels:
+ *
+ *   ct_sinkhorn_grad          gradient of the debiased Sinkhorn divergence
+ *                             (Sec. II-B, eqs. 5-7) w.r.t. the trajectory samples
+ *                             and the reference weights, and its value;
+ *   ct_sinkhorn_grad_batched  the same for many independent problems of uneven
+ *                             size in one persistent launch;
+ *   ct_svgd_grad              Stein variational flow (Sec. II-B, eq. 4) with an
+ *                             RBF kernel and an analytic Gaussian-mixture score;
+ *   ct_lqr_track              linear-quadratic flow matching (Sec. II-C, eqs. 8-10),
+ *                             a sequential FP64 host solve;
+ *   ct_plan                   the outer planning loop (Sec. II-A eqs. 2-3 with
+ *                             Sec. II-C): flow on the GPU, LQR on the host.
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Point sets are row-major float32 arrays [N][d] (point after point), d = 2 or 3.
+ * - Pointers marked "device" are HIP device (or managed) memory; "host" ones are
+ *   ordinary host memory.  The caller owns every buffer.  GPU entry points never
+ *   allocate: they use the caller's workspace `ws` (device, 256-byte aligned,
+ *   at least the size returned by the matching *_workspace_size call).  Its
+ *   contents need not be initialised and are clobbered.
+ * - GPU entry points are asynchronous on `stream` (a hipStream_t; NULL = the
+ *   null stream): they enqueue kernels and return without synchronising, except
+ *   ct_plan, which is synchronous.  Two calls that share a workspace must be
+ *   ordered on one stream.
+ * - Arguments are validated on the host before anything is enqueued; an invalid
+ *   call returns a negative status, enqueues nothing and leaves a message for
+ *   ct_last_error() (per thread).
+ * - The arithmetic is float32 on the GPU and float64 on the host (LQR).
+ */
+#ifndef CT_H
+#define CT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ct_status;
+
+#define CT_OK 0
+#define CT_E_ARG (-1)         /* null pointer, out-of-range scalar or bad flag */
+#define CT_E_SHAPE (-2)       /* sizes inconsistent or unsupported (d, T, M, B) */
+#define CT_E_WORKSPACE (-4)   /* ws too small or misaligned */
+#define CT_E_HIP (-5)         /* a HIP runtime call failed (message has the HIP error) */
+#define CT_E_UNSUPPORTED (-6) /* feature not available for this input */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ct_last_error(void);
+/* Library version string. */
+const char* ct_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* Sinkhorn divergence gradient (Sec. II-B, eqs. 5-7)                          */
+/* ------------------------------------------------------------------------- */
+
+/* Option flags (bitwise or). */
+#define CT_DEBIAS 1u      /* S = OT(a,b) - OT(a,a)/2 - OT(b,b)/2 (eq. 6); else S = OT(a,b) */
+#define CT_GRAD_W 2u      /* compute dS/dw */
+#define CT_VALUE 4u       /* compute S */
+#define CT_WARM_START 8u  /* start from the potentials in `pot` instead of zeros */
+#define CT_REF_CACHED 16u /* `pot` holds a converged reference self potential q: skip its iterations */
+#define CT_SAFE_LSE 32u   /* track the running maximum in every sweep (no lagged shift) */
+
+typedef struct ct_sinkhorn_opts {
+    int32_t d;      /* 2 or 3 */
+    int32_t iters;  /* Sinkhorn iterations K >= 0 (0: only the final extrapolation pass) */
+    float eps;      /* entropic weight (the paper's omega), > 0, in squared-distance units */
+    uint32_t flags; /* CT_* flags above */
+} ct_sinkhorn_opts;
+
+/* Workspace bytes needed by ct_sinkhorn_grad for these sizes and options. */
+size_t ct_sinkhorn_workspace_size(int64_t T, int64_t M, const ct_sinkhorn_opts* o);
+
+/*
+ * Debiased Sinkhorn divergence S between the trajectory samples x_1..x_T (equal
+ * masses a_i = 1/T: eq. 1 at equal time steps) and the reference samples
+ * y_1..y_M with masses b_j = w_j / sum(w) (eq. 5 with the squared-norm cost and
+ * relative-entropy regulariser, eq. 6), solved by log-domain Sinkhorn sweeps:
+ * K Gauss-Seidel iterations f <- T_b(g), g <- T_a(f) for the cross problem and
+ * K averaged iterations p <- (p + T_a(p))/2, q <- (q + T_b(q))/2 for the self
+ * problems, all from zero (or `pot` with CT_WARM_START), followed by one
+ * extrapolation pass f+ = T_b(g), p+ = T_a(p), g+ = T_a(f+), q+ = T_b(q), where
+ * T_b(g)_i = -eps log sum_j b_j exp((g_j - |x_i - y_j|^2)/eps).
+ *
+ * Outputs (eq. 7 by the envelope theorem):
+ *   grad_x[i] = dS/dx_i = 2 a_i (Ds_i - Dy_i), with Dy_i (Ds_i) the mean of
+ *               y_j - x_i (x_k - x_i) under the row-normalised cross (self) plan;
+ *               without CT_DEBIAS, -2 a_i Dy_i.  The planner's flow is -T*grad_x.
+ *   grad_w[j] = dS/dw_j = (G_j - <b,G>) / sum(w), G = g+ - q+ (g+ without debias).
+ *   value     = <a,f+> + <b,g> - (<a,p+> + <a,p>)/2 - (<b,q+> + <b,q>)/2.
+ *
+ *   x       device [T][d]       trajectory samples
+ *   y       device [M][d]       reference samples
+ *   w       device [M] or NULL  reference weights > 0 (NULL: all equal)
+ *   grad_x  device [T][d]       out
+ *   grad_w  device [M] or NULL  out (requires CT_GRAD_W)
+ *   value   device [1] or NULL  out (requires CT_VALUE)
+ *   pot     device [2T+2M] or NULL  f[T], g[M], p[T], q[M]: last iterates out;
+ *                               starting iterates in with CT_WARM_START (and q in
+ *                               with CT_REF_CACHED).  Required for those flags.
+ *   pot_plus device [2T+2M] or NULL  f+, g+, p+, q+ out (g+, q+ only when
+ *                               CT_VALUE or CT_GRAD_W; p+, q+ only with CT_DEBIAS)
+ *   aux     device [8] or NULL  out: OT(a,b), OT(a,a), OT(b,b), column-marginal
+ *                               L1 residual sum_j |colsum_j - b_j| of the plan
+ *                               (f+, g), rows recomputed with a tracked maximum,
+ *                               number of non-finite inputs, 0, 0, 0
+ *                               (entries 0-3 need CT_VALUE or CT_GRAD_W)
+ * Errors: CT_E_ARG (null x/y/grad_x/ws, eps <= 0 or non-finite, iters < 0, grad_w
+ * without CT_GRAD_W, pot missing for CT_WARM_START/CT_REF_CACHED, unknown flag),
+ * CT_E_SHAPE (d not 2/3, T < 1, M < 1, T or M > 2^30), CT_E_WORKSPACE, CT_E_HIP.
+ */
+ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const float* w, int64_t M,
+                           const ct_sinkhorn_opts* o, float* grad_x, float* grad_w, float* value,
+                           float* pot, float* pot_plus, float* aux, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/*
+ * Many independent problems b = 0..B-1 of uneven size (the batched form of
+ * ct_sinkhorn_grad, same definitions and options for every problem), evaluated
+ * by one persistent kernel that walks a dependency-ordered work list.
+ *   T_off, M_off  host [B+1]  prefix offsets: problem b owns x rows
+ *                             T_off[b]..T_off[b+1]-1 and y rows M_off[b]..M_off[b+1]-1
+ *                             (every problem needs T_b >= 1, M_b >= 1)
+ *   x, y, w, grad_x, grad_w   concatenations in that order (w may be NULL)
+ *   value         device [B] or NULL (requires CT_VALUE)
+ * CT_WARM_START and CT_REF_CACHED are not supported here (CT_E_ARG).
+ * The work list is rebuilt on the host each call and copied into `ws` on
+ * `stream`; the copy is synchronous with respect to the host (pageable source).
+ */
+size_t ct_sinkhorn_batched_workspace_size(int32_t B, const int64_t* T_off, const int64_t* M_off,
+                                          const ct_sinkhorn_opts* o);
+ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* T_off, const int64_t* M_off,
+                                   const float* x, const float* y, const float* w,
+                                   const ct_sinkhorn_opts* o, float* grad_x, float* grad_w,
+                                   float* value, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Stein variational flow (Sec. II-B, eq. 4)                                   */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Target density: a Gaussian mixture with diagonal covariances, optionally mixed
+ * with a uniform density of mass `floor` on the unit box [0,1]^d:
+ *   q(x) = (1 - floor) sum_k pi_k N(x; mu_k, diag sigma_k^2) + floor 1[x in [0,1]^d].
+ * Only its score grad log q is used (Sec. II-B: the Stein flow needs only the score).
+ */
+typedef struct ct_gmm {
+    int32_t K;            /* components, 1..64 */
+    const float* weights; /* device [K]  pi_k > 0 */
+    const float* means;   /* device [K][d] */
+    const float* sigmas;  /* device [K][d]  > 0 */
+    float floor;          /* uniform mass in [0, 1) */
+} ct_gmm;
+
+size_t ct_svgd_workspace_size(int64_t T, int32_t d);
+
+/*
+ * phi_i = 1/T sum_j k_ij [ score(x_j) + (2/h)(x_i - x_j) ],  k_ij = exp(-|x_i - x_j|^2 / h)
+ * (eq. 4; the j = i term included).  With h <= 0 the bandwidth is the median
+ * heuristic h = med^2 / ln T, med the median of the T(T-1)/2 distances
+ * |x_i - x_j| (i < j; mean of the two middle ones for an even count; h = 1 for
+ * T = 1), found by an exact radix selection on the device.
+ *   x       device [T][d]
+ *   q       host struct with device arrays (see ct_gmm)
+ *   phi     device [T][d] out
+ *   score   device [T][d] or NULL  out: grad log q(x_i)
+ *   h_used  device [1] or NULL     out: the bandwidth used
+ * Errors: CT_E_ARG (null x/q/phi/ws, K out of range, floor outside [0,1), h not
+ * finite), CT_E_SHAPE (d, T < 1 or T > 2^30), CT_E_WORKSPACE, CT_E_HIP.
+ */
+ct_status ct_svgd_grad(const float* x, int64_t T, int32_t d, const ct_gmm* q, float h, float* phi,
+                       float* score, float* h_used, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Linear-quadratic flow matching (Sec. II-C, eqs. 8-10), host FP64            */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Forward-Euler discretisation of eqs. 9-10 at step dt:
+ *   z_0 = 0,  z_{t+1} = (I + dt A_t) z_t + dt B_t v_t,   t = 0..T-1
+ *   minimise sum_t dt |a_t - z_{t+1}|^2_Q + dt |v_t|^2_R
+ * solved exactly by the backward Riccati recursion with the affine tracking
+ * term and a forward rollout.  Sequential, O(T n^3).
+ *   A host [T][n][n]  continuous-time Jacobians df/ds along the trajectory (eq. 8)
+ *   B host [T][n][m]  df/du
+ *   a host [T][n]     reference flow, the target of z_{t+1}
+ *   Q host [n][n], R host [m][m]  symmetric, Q >= 0, R > 0
+ *   v host [T][m] out;  z host [T+1][n] out or NULL
+ * Errors: CT_E_ARG (null pointers, dt <= 0), CT_E_SHAPE (T < 1, n or m outside
+ * 1..8), CT_E_UNSUPPORTED (a Riccati step is not positive definite).
+ */
+ct_status ct_lqr_track(int64_t T, int32_t n, int32_t m, double dt, const double* A, const double* B,
+                       const double* a, const double* Q, const double* R, double* v, double* z);
+
+/* ------------------------------------------------------------------------- */
+/* Outer planning loop (Sec. II-A eqs. 2-3, Sec. II-C)                         */
+/* ------------------------------------------------------------------------- */
+
+#define CT_DYN_DOUBLE_INTEGRATOR 0 /* state (p, v) in R^{2d}, control acceleration in R^d */
+#define CT_DYN_UNICYCLE 1          /* state (p_x, p_y, heading), control (speed, turn rate); d = 2 */
+#define CT_FLOW_SINKHORN 0
+#define CT_FLOW_SVGD 1
+
+typedef struct ct_plan_problem {
+    int32_t dynamics; /* CT_DYN_* */
+    int32_t d;        /* position dimension (2 or 3; 2 for the unicycle) */
+    int64_t T;        /* control steps = trajectory samples */
+    double dt;        /* > 0 */
+    const double* s0; /* host [n] initial state */
+} ct_plan_problem;
+
+typedef struct ct_plan_opts {
+    int32_t flow;        /* CT_FLOW_* */
+    int32_t outer;       /* outer iterations >= 1 */
+    double step;         /* control update u <- u + step v* */
+    const double* Q;     /* host [d][d]: weight of the position block */
+    const double* R;     /* host [m][m] */
+    ct_sinkhorn_opts sk; /* Sinkhorn settings (flow = CT_FLOW_SINKHORN) */
+    float svgd_h;        /* Stein bandwidth, <= 0 for the median heuristic */
+} ct_plan_opts;
+
+size_t ct_plan_workspace_size(const ct_plan_problem* p, const ct_plan_opts* o, int64_t M);
+
+/*
+ * Each outer iteration: roll the dynamics forward with Euler steps from s0 under
+ * u; take the positions of s_1..s_T as the trajectory samples; evaluate the
+ * reference flow on the GPU (Sinkhorn: -T dS/dx_i; Stein: phi_i); linearise the
+ * dynamics along (s_t, u_t) (eq. 8); solve ct_lqr_track with the flow as the
+ * target of the position block; update u <- u + step v*.  Synchronous.
+ *   y, w    device reference samples/weights (Sinkhorn flow; w may be NULL)
+ *   q       host struct (Stein flow), else NULL
+ *   u       host [T][m] controls, in/out
+ *   s       host [T+1][n] out: final rollout (after the last update), or NULL
+ *   hist    host [outer] out: S (Sinkhorn) or mean |phi_i| (Stein) at the start
+ *           of each outer iteration, or NULL
+ */
+ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, const float* y, const float* w,
+                  int64_t M, const ct_gmm* q, double* u, double* s, double* hist, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Autotuning of the sweep kernels' tile and split schedule                    */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Times the candidate schedules (queries per lane, blocks per CU) of the
+ * Sinkhorn sweep kernel for this problem shape on `stream` (synchronously) and
+ * records the fastest in the process-wide tuning table, keyed by (d, size
+ * class of T, size class of M).  Later ct_sinkhorn_grad / _batched calls of
+ * that class use it.  `ws` must hold ct_sinkhorn_workspace_size(T, M, o) bytes.
+ * Must not be called while `stream` is being captured.
+ */
+ct_status ct_autotune_sinkhorn(int64_t T, int64_t M, const ct_sinkhorn_opts* o, void* ws,
+                               size_t ws_bytes, void* stream);
+/* Number of tuned entries, and entry i as (d, T class, M class, R, blocks/CU, us). */
+int32_t ct_tuning_count(void);
+ct_status ct_tuning_entry(int32_t i, int32_t* out6);
+/* Save / load the tuning table as text (one entry per line). */
+ct_status ct_tuning_save(const char* path);
+ct_status ct_tuning_load(const char* path);
+void ct_tuning_clear(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CT_H */

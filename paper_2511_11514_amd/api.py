@@ -1,0 +1,308 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only).
+
+Every function here checks dtypes/devices, allocates the outputs and the
+workspace with torch, and calls the matching libct.so entry point on the
+current torch stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+from torch.autograd.function import once_differentiable
+
+from . import _lib as L
+from ._lib import check, lib
+
+
+def version() -> str:
+    return lib().ct_version().decode()
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _req(t: torch.Tensor, name: str, dev: Optional[torch.device] = None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor")
+    if dev is not None and t.device != dev:
+        raise ValueError(f"{name} is on {t.device}, expected {dev}")
+    return t.contiguous()
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, dev: torch.device) -> torch.Tensor:
+    if nbytes == 0:
+        raise ValueError("invalid problem shape (workspace size 0)")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+
+
+@dataclass
+class SinkhornOut:
+    grad_x: torch.Tensor
+    grad_w: Optional[torch.Tensor]
+    value: Optional[torch.Tensor]
+    pot: Optional[torch.Tensor]        # [2T+2M] f, g, p, q (last iterates)
+    pot_plus: Optional[torch.Tensor]   # [2T+2M] f+, g+, p+, q+
+    aux: Optional[torch.Tensor]        # [8]
+
+
+def _opts(d: int, eps: float, iters: int, flags: int) -> L.SinkhornOpts:
+    return L.SinkhornOpts(int(d), int(iters), float(eps), int(flags))
+
+
+def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = None, *,
+                  eps: float, iters: int, debias: bool = True, value: bool = False,
+                  grad_w: bool = False, init: Optional[torch.Tensor] = None,
+                  ref_q: Optional[torch.Tensor] = None, safe: bool = False,
+                  potentials: bool = False, aux: bool = False) -> SinkhornOut:
+    """Gradient of the (debiased) Sinkhorn divergence; see ct_sinkhorn_grad.
+
+    x [T,d], y [M,d], w [M] or None: float32 GPU tensors.
+    init: optional [2T+2M] starting potentials (f, g, p, q) -> CT_WARM_START.
+    ref_q: optional [M] converged reference self potential -> CT_REF_CACHED.
+    """
+    dev = x.device
+    x = _req(x, "x")
+    y = _req(y, "y", dev)
+    if w is not None:
+        w = _req(w, "w", dev)
+    T, d = x.shape
+    M = y.shape[0]
+    if y.shape[1] != d:
+        raise ValueError("x and y must have the same dimension")
+    flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
+        (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0)
+    pot = None
+    if init is not None or ref_q is not None or potentials:
+        pot = torch.zeros(2 * T + 2 * M, dtype=torch.float32, device=dev)
+        if init is not None:
+            pot.copy_(_req(init, "init", dev).reshape(-1))
+            flags |= L.CT_WARM_START
+        if ref_q is not None:
+            pot[2 * T + M:].copy_(_req(ref_q, "ref_q", dev).reshape(-1))
+            flags |= L.CT_REF_CACHED
+    o = _opts(d, eps, iters, flags)
+    gx = torch.empty_like(x)
+    gw = torch.empty(M, dtype=torch.float32, device=dev) if grad_w else None
+    val = torch.empty(1, dtype=torch.float32, device=dev) if value else None
+    pp = torch.empty(2 * T + 2 * M, dtype=torch.float32, device=dev) if potentials else None
+    ax = torch.empty(8, dtype=torch.float32, device=dev) if aux else None
+    nbytes = lib().ct_sinkhorn_workspace_size(T, M, ctypes.byref(o))
+    ws = _workspace(nbytes, dev)
+    st = lib().ct_sinkhorn_grad(_p(x), T, _p(y), _p(w), M, ctypes.byref(o), _p(gx), _p(gw),
+                                _p(val), _p(pot), _p(pp), _p(ax), _p(ws), nbytes, _stream(dev))
+    check("ct_sinkhorn_grad", st)
+    return SinkhornOut(gx, gw, val, pot if potentials else None, pp, ax)
+
+
+class SinkhornDivergence(torch.autograd.Function):
+    """S(x, (y, w)) as an autograd function (Sec. II-B, eq. 7 "through
+    auto-differentiation").  The forward pass computes S together with dS/dx and
+    dS/dw (envelope theorem on the extrapolated potentials); the backward pass
+    only scales them by the incoming gradient, so no second solve is needed."""
+
+    @staticmethod
+    def forward(ctx, x, y, w, eps: float, iters: int, debias: bool = True):
+        need_w = bool(w is not None and ctx.needs_input_grad[2])
+        out = sinkhorn_grad(x.detach(), y.detach(), None if w is None else w.detach(), eps=eps,
+                            iters=iters, debias=debias, value=True, grad_w=need_w)
+        ctx.save_for_backward(out.grad_x, out.grad_w if need_w else None)
+        ctx.need_w = need_w
+        return out.value.reshape(())
+
+    @staticmethod
+    @once_differentiable
+    def backward(ctx, gS):
+        gx, gw = ctx.saved_tensors
+        return gS * gx, None, (gS * gw if ctx.need_w else None), None, None, None
+
+
+def sinkhorn_divergence(x, y, w=None, *, eps: float, iters: int, debias: bool = True):
+    return SinkhornDivergence.apply(x, y, w, eps, iters, debias)
+
+
+@dataclass
+class BatchedOut:
+    grad_x: List[torch.Tensor]
+    grad_w: Optional[List[torch.Tensor]]
+    value: Optional[torch.Tensor]
+
+
+def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor],
+                          ws: Optional[Sequence[torch.Tensor]] = None, *, eps: float, iters: int,
+                          debias: bool = True, value: bool = False, grad_w: bool = False,
+                          safe: bool = False) -> BatchedOut:
+    """Many independent problems (ragged T_b, M_b) in one persistent launch."""
+    B = len(xs)
+    if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
+        raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
+    dev = xs[0].device
+    d = xs[0].shape[1]
+    T_off = np.zeros(B + 1, dtype=np.int64)
+    M_off = np.zeros(B + 1, dtype=np.int64)
+    for b in range(B):
+        T_off[b + 1] = T_off[b] + xs[b].shape[0]
+        M_off[b + 1] = M_off[b] + ys[b].shape[0]
+    x = _req(torch.cat([_req(t, "x", dev) for t in xs]), "x")
+    y = _req(torch.cat([_req(t, "y", dev) for t in ys]), "y")
+    w = None if ws is None else _req(torch.cat([_req(t, "w", dev) for t in ws]), "w")
+    flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
+        (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0)
+    o = _opts(d, eps, iters, flags)
+    to = T_off.ctypes.data_as(L.PI64)
+    mo = M_off.ctypes.data_as(L.PI64)
+    gx = torch.empty_like(x)
+    gw = torch.empty(int(M_off[-1]), dtype=torch.float32, device=dev) if grad_w else None
+    val = torch.empty(B, dtype=torch.float32, device=dev) if value else None
+    nbytes = lib().ct_sinkhorn_batched_workspace_size(B, to, mo, ctypes.byref(o))
+    wsb = _workspace(nbytes, dev)
+    st = lib().ct_sinkhorn_grad_batched(B, to, mo, _p(x), _p(y), _p(w), ctypes.byref(o), _p(gx),
+                                        _p(gw), _p(val), _p(wsb), nbytes, _stream(dev))
+    check("ct_sinkhorn_grad_batched", st)
+    gxs = [gx[T_off[b]:T_off[b + 1]] for b in range(B)]
+    gws = None if gw is None else [gw[M_off[b]:M_off[b + 1]] for b in range(B)]
+    return BatchedOut(gxs, gws, val)
+
+
+@dataclass
+class GMM:
+    """Gaussian mixture on the GPU: weights [K], means [K,d], sigmas [K,d], uniform floor."""
+    weights: torch.Tensor
+    means: torch.Tensor
+    sigmas: torch.Tensor
+    floor: float = 0.0
+
+    @staticmethod
+    def from_numpy(g, device) -> "GMM":
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=device)
+        return GMM(t(g.weights), t(g.means), t(g.sigmas), float(g.floor))
+
+    def desc(self) -> L.GMMDesc:
+        return L.GMMDesc(int(self.weights.shape[0]), self.weights.data_ptr(),
+                         self.means.data_ptr(), self.sigmas.data_ptr(), float(self.floor))
+
+
+def svgd_grad(x: torch.Tensor, gmm: GMM, h: Optional[float] = None, *, return_score: bool = False):
+    """Stein variational flow phi (eq. 4) with the RBF kernel and the mixture's
+    score; h None/<=0 selects the median heuristic.  Returns (phi, h_used[, score])."""
+    dev = x.device
+    x = _req(x, "x")
+    T, d = x.shape
+    for name in ("weights", "means", "sigmas"):
+        setattr(gmm, name, _req(getattr(gmm, name), name, dev))
+    phi = torch.empty_like(x)
+    score = torch.empty_like(x) if return_score else None
+    hu = torch.empty(1, dtype=torch.float32, device=dev)
+    nbytes = lib().ct_svgd_workspace_size(T, d)
+    ws = _workspace(nbytes, dev)
+    desc = gmm.desc()
+    st = lib().ct_svgd_grad(_p(x), T, d, ctypes.byref(desc), float(h if h else 0.0), _p(phi),
+                            _p(score), _p(hu), _p(ws), nbytes, _stream(dev))
+    check("ct_svgd_grad", st)
+    return (phi, hu, score) if return_score else (phi, hu)
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(L.PD)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def lqr_track(A, B, a, Q, R, dt: float):
+    """Host FP64 tracking LQR (eqs. 9-10); returns (v [T,m], z [T+1,n])."""
+    A, B, a, Q, R = (_f64(t) for t in (A, B, a, Q, R))
+    T, n, m = B.shape
+    v = np.empty((T, m))
+    z = np.empty((T + 1, n))
+    st = lib().ct_lqr_track(T, n, m, float(dt), _dp(A), _dp(B), _dp(a), _dp(Q), _dp(R), _dp(v), _dp(z))
+    check("ct_lqr_track", st)
+    return v, z
+
+
+_DYN = {"double_integrator": L.CT_DYN_DOUBLE_INTEGRATOR, "unicycle": L.CT_DYN_UNICYCLE}
+_FLOW = {"sinkhorn": L.CT_FLOW_SINKHORN, "svgd": L.CT_FLOW_SVGD}
+
+
+def plan(dynamics: str, s0, u, dt: float, Q, R, flow: str, outer: int, step: float = 1.0, *,
+         y: Optional[torch.Tensor] = None, w: Optional[torch.Tensor] = None,
+         gmm: Optional[GMM] = None, eps: float = 0.01, iters: int = 100, debias: bool = True,
+         svgd_h: float = 0.0, device=None):
+    """Outer planning loop (ct_plan).  Returns (u [T,m], s [T+1,n], hist [outer])."""
+    s0 = _f64(s0)
+    u = _f64(u).copy()
+    Q = _f64(Q)
+    R = _f64(R)
+    T, m = u.shape
+    d = Q.shape[0]
+    n = s0.shape[0]
+    dev = torch.device(device) if device is not None else (
+        y.device if y is not None else gmm.weights.device)
+    prob = L.PlanProblem(_DYN[dynamics], d, T, float(dt), _dp(s0))
+    sk = _opts(d, eps, iters, L.CT_DEBIAS if debias else 0)
+    opts = L.PlanOpts(_FLOW[flow], int(outer), float(step), _dp(Q), _dp(R), sk, float(svgd_h))
+    M = 0
+    if y is not None:
+        y = _req(y, "y", dev)
+        M = y.shape[0]
+        if w is not None:
+            w = _req(w, "w", dev)
+    desc = None
+    if gmm is not None:
+        for name in ("weights", "means", "sigmas"):
+            setattr(gmm, name, _req(getattr(gmm, name), name, dev))
+        desc = gmm.desc()
+    s = np.empty((T + 1, n))
+    hist = np.empty(outer)
+    nbytes = lib().ct_plan_workspace_size(ctypes.byref(prob), ctypes.byref(opts), M)
+    ws = _workspace(nbytes, dev)
+    st = lib().ct_plan(ctypes.byref(prob), ctypes.byref(opts), _p(y), _p(w), M,
+                       ctypes.byref(desc) if desc is not None else None, _dp(u), _dp(s), _dp(hist),
+                       _p(ws), nbytes, _stream(dev))
+    check("ct_plan", st)
+    return u, s, hist
+
+
+def autotune_sinkhorn(T: int, M: int, d: int, eps: float, device="cuda") -> None:
+    """Time the candidate sweep schedules for this shape and record the best."""
+    dev = torch.device(device)
+    o = _opts(d, eps, 1, L.CT_DEBIAS | L.CT_VALUE | L.CT_GRAD_W)
+    nbytes = lib().ct_sinkhorn_workspace_size(T, M, ctypes.byref(o))
+    ws = _workspace(nbytes, dev)
+    st = lib().ct_autotune_sinkhorn(T, M, ctypes.byref(o), _p(ws), nbytes, _stream(dev))
+    check("ct_autotune_sinkhorn", st)
+
+
+def tuning_table():
+    n = lib().ct_tuning_count()
+    out = []
+    buf = (ctypes.c_int32 * 6)()
+    for i in range(n):
+        check("ct_tuning_entry", lib().ct_tuning_entry(i, buf))
+        out.append(tuple(buf))
+    return out
+
+
+def tuning_save(path: str) -> None:
+    check("ct_tuning_save", lib().ct_tuning_save(path.encode()))
+
+
+def tuning_load(path: str) -> None:
+    check("ct_tuning_load", lib().ct_tuning_load(path.encode()))
+
+
+def tuning_clear() -> None:
+    lib().ct_tuning_clear()

@@ -1,0 +1,76 @@
+"""CPU checks of the C ABI: the library loads, exports every function declared
+in include/ct.h, and rejects invalid arguments on the host before any GPU work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ct.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ct_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    from paper_2511_11514_amd import lib
+    L = lib()
+    names = _declared()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert L.ct_version().startswith(b"ct ")
+
+
+def test_binding_declares_every_symbol():
+    from paper_2511_11514_amd import _lib
+    assert set(_declared()) <= set(_lib._SIGS)
+
+
+def _call_sinkhorn(**kw):
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    args = dict(x=1, T=10, y=1, w=None, M=20, o=_lib.SinkhornOpts(2, 10, 0.01, _lib.CT_DEBIAS),
+                gx=1, gw=None, val=None, pot=None, pp=None, aux=None, ws=256, nb=1 << 30)
+    args.update(kw)
+    P = ctypes.c_void_p
+    return L.ct_sinkhorn_grad(P(args["x"]), args["T"], P(args["y"]), P(args["w"]), args["M"],
+                              ctypes.byref(args["o"]), P(args["gx"]), P(args["gw"]),
+                              P(args["val"]), P(args["pot"]), P(args["pp"]), P(args["aux"]),
+                              P(args["ws"]), args["nb"], None)
+
+
+def test_sinkhorn_rejects_bad_arguments_before_launch():
+    from paper_2511_11514_amd import _lib
+    O = _lib.SinkhornOpts
+    assert _call_sinkhorn(x=None) == _lib.CT_E_ARG
+    assert _call_sinkhorn(T=0) == _lib.CT_E_SHAPE
+    assert _call_sinkhorn(M=-3) == _lib.CT_E_SHAPE
+    assert _call_sinkhorn(o=O(4, 10, 0.01, 1)) == _lib.CT_E_SHAPE
+    assert _call_sinkhorn(o=O(2, 10, 0.0, 1)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, 10, float("nan"), 1)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, -1, 0.01, 1)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, 10, 0.01, 1 << 12)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_GRAD_W)) == _lib.CT_E_ARG   # grad_w missing
+    assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_WARM_START)) == _lib.CT_E_ARG  # pot missing
+    assert _call_sinkhorn(gx=None) == _lib.CT_E_ARG
+    assert _call_sinkhorn(ws=None) == _lib.CT_E_ARG
+    assert _call_sinkhorn(ws=257) == _lib.CT_E_WORKSPACE
+    assert _call_sinkhorn(nb=16) == _lib.CT_E_WORKSPACE
+    msg = _lib.lib().ct_last_error().decode()
+    assert "workspace" in msg
+
+
+def test_workspace_size_is_monotone_and_rejects_bad_shapes():
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    o = _lib.SinkhornOpts(2, 10, 0.01, 1)
+    a = L.ct_sinkhorn_workspace_size(1000, 2000, ctypes.byref(o))
+    b = L.ct_sinkhorn_workspace_size(2000, 4000, ctypes.byref(o))
+    assert 0 < a < b
+    assert L.ct_sinkhorn_workspace_size(0, 10, ctypes.byref(o)) == 0
+    bad = _lib.SinkhornOpts(5, 10, 0.01, 1)
+    assert L.ct_sinkhorn_workspace_size(10, 10, ctypes.byref(bad)) == 0

@@ -1,0 +1,132 @@
+"""GPU parity of ct_sinkhorn_grad against the FP64 oracle (Sec. II-B, eqs. 5-7).
+
+Tolerance: 1e-5 norm-wise relative error on gradients, gauge-fixed potentials
+and the value (the accuracy bar of the float32 path against the float64 oracle).
+Sizes span several key tiles, several query blocks and ragged tails."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import gauge, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _run(ct, x, y, w, eps, iters, debias=True, init=None, safe=False):
+    dev = torch.device("cuda")
+    t = lambda a: torch.as_tensor(a, device=dev)
+    out = ct.sinkhorn_grad(t(x), t(y), None if w is None else t(w), eps=eps, iters=iters,
+                           debias=debias, value=True, grad_w=True, potentials=True, aux=True,
+                           init=None if init is None else t(init.astype(np.float32)), safe=safe)
+    torch.cuda.synchronize()
+    return {k: (None if v is None else v.cpu().numpy()) for k, v in out.__dict__.items()}
+
+
+def _oracle(x, y, w, eps, iters, debias=True, init=None):
+    T, M = len(x), len(y)
+    if init is not None:
+        init = (init[:T], init[T:T + M], init[T + M:2 * T + M], init[2 * T + M:])
+    return oracle.sinkhorn(x, y, w, eps=eps, iters=iters, debias=debias, init=init)
+
+
+def _compare(g, r, T, M, w, debias=True, tol=TOL):
+    b = None if w is None else np.asarray(w, np.float64) / np.sum(w, dtype=np.float64)
+    errs = {}
+    errs["grad_x"] = rel(g["grad_x"], r.grad_x)
+    errs["grad_w"] = rel(g["grad_w"], r.grad_w)
+    errs["value"] = abs(float(g["value"][0]) - r.value) / max(abs(r.value), 1e-30)
+    pot, pp = g["pot"], g["pot_plus"]
+    f1, g1 = gauge(pot[:T], pot[T:T + M], T, M, b)
+    f2, g2 = gauge(r.f, r.g, T, M, b)
+    errs["f"] = rel(f1, f2)
+    errs["g"] = rel(g1, g2)
+    errs["f_plus"] = rel(pp[:T], r.f_plus)
+    errs["g_plus"] = rel(pp[T:T + M], r.g_plus)
+    if debias:
+        errs["p"] = rel(pot[T + M:2 * T + M], r.p)
+        errs["q"] = rel(pot[2 * T + M:], r.q)
+        errs["p_plus"] = rel(pp[T + M:2 * T + M], r.p_plus)
+        errs["q_plus"] = rel(pp[2 * T + M:], r.q_plus)
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"errors above {tol}: {bad} (all: {errs})"
+    return errs
+
+
+@pytest.mark.parametrize("d,T,M,eps,iters", [
+    (2, 1000, 3001, 0.01, 50),
+    (2, 2500, 700, 0.005, 40),
+    (3, 777, 2049, 0.02, 30),
+])
+def test_parity_random_walk_vs_gmm(ct, d, T, M, eps, iters):
+    cfg = W.CONFIGS["grad_2d"] if d == 2 else W.CONFIGS["autograd_3d"]
+    x, y, w, _g = W.config_inputs(cfg, T=T, M=M)
+    g = _run(ct, x, y, w, eps, iters)
+    r = _oracle(x, y, w, eps, iters)
+    errs = _compare(g, r, T, M, w)
+    print(f"d={d} T={T} M={M} eps={eps} K={iters}: " +
+          " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+
+
+def test_parity_weighted_and_not_debiased(ct):
+    rng = np.random.default_rng(7)
+    x, y, _w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=600, M=1500)
+    w = W.positive_weights(rng, 1500)
+    g = _run(ct, x, y, w, 0.01, 40, debias=False)
+    r = _oracle(x, y, w, 0.01, 40, debias=False)
+    _compare(g, r, 600, 1500, w, debias=False)
+    g = _run(ct, x, y, w, 0.01, 40)
+    r = _oracle(x, y, w, 0.01, 40)
+    _compare(g, r, 600, 1500, w)
+
+
+def test_zero_iterations_and_safe_mode(ct):
+    x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=513, M=1025)
+    for safe in (False, True):
+        g = _run(ct, x, y, w, 0.01, 0, safe=safe)
+        r = _oracle(x, y, w, 0.01, 0)
+        _compare(g, r, 513, 1025, w)
+    g = _run(ct, x, y, w, 0.01, 25, safe=True)
+    r = _oracle(x, y, w, 0.01, 25)
+    _compare(g, r, 513, 1025, w)
+
+
+def test_warm_start_and_row_rescue(ct):
+    """A warm start far from the fixed point makes the lagged shift useless for
+    the first sweep: the affected rows must be recomputed exactly."""
+    T, M = 400, 900
+    x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=T, M=M)
+    init = np.zeros(2 * T + 2 * M, dtype=np.float32)
+    init[:T] = 3.0          # f far too large: 2^(-(kappa*3)) underflows every row
+    init[T:T + M] = -1.0
+    init[T + M:2 * T + M] = -2.0
+    g = _run(ct, x, y, w, 0.01, 20, init=init)
+    assert g["aux"][4] > 0, "rescue path was not exercised"
+    r = _oracle(x, y, w, 0.01, 20, init=init.astype(np.float64))
+    _compare(g, r, T, M, w)
+
+
+def test_single_point_closed_form(ct):
+    x = np.array([[0.2, 0.7]], np.float32)
+    y = np.array([[0.5, 0.1]], np.float32)
+    g = _run(ct, x, y, None, 0.01, 5)
+    diff = (x[0] - y[0]).astype(np.float64)
+    assert abs(g["value"][0] - diff @ diff) < 1e-6
+    np.testing.assert_allclose(g["grad_x"][0], 2 * diff, rtol=1e-5)
+    assert abs(g["grad_w"][0]) < 1e-7
+
+
+def test_tiny_and_identical(ct):
+    rng = np.random.default_rng(3)
+    x = rng.uniform(size=(5, 2)).astype(np.float32)
+    g = _run(ct, x, x.copy(), None, 0.1, 400)
+    r = _oracle(x, x.copy(), None, 0.1, 400)
+    assert np.abs(g["grad_x"]).max() < 1e-5 * np.abs(x).max()
+    np.testing.assert_allclose(g["grad_x"], r.grad_x, atol=2e-6)
+    y = rng.uniform(size=(3, 2)).astype(np.float32)
+    g = _run(ct, x, y, None, 0.05, 30)
+    r = _oracle(x, y, None, 0.05, 30)
+    _compare(g, r, 5, 3, None)
