@@ -110,11 +110,13 @@ size_t ct_sinkhorn_workspace_size(int64_t T, int64_t M, const ct_sinkhorn_opts* 
  *                               with CT_REF_CACHED).  Required for those flags.
  *   pot_plus device [2T+2M] or NULL  f+, g+, p+, q+ out (g+, q+ only when
  *                               CT_VALUE or CT_GRAD_W; p+, q+ only with CT_DEBIAS)
- *   aux     device [8] or NULL  out: OT(a,b), OT(a,a), OT(b,b), column-marginal
- *                               L1 residual sum_j |colsum_j - b_j| of the plan
- *                               (f+, g), rows recomputed with a tracked maximum,
- *                               number of non-finite inputs, 0, 0, 0
- *                               (entries 0-3 need CT_VALUE or CT_GRAD_W)
+ *   aux     device [8] or NULL  out: [0] OT(a,b), [1] OT(a,a), [2] OT(b,b),
+ *                               [3] column-marginal L1 residual sum_j |colsum_j - b_j|
+ *                               of the plan (f+, g) (entries 0-3 need CT_VALUE or
+ *                               CT_GRAD_W, else 0), [4] number of rows whose lagged
+ *                               shift was unusable and that were recomputed with a
+ *                               tracked maximum, [5] number of non-finite inputs or
+ *                               non-positive weights, [6], [7] zero
  * Errors: CT_E_ARG (null x/y/grad_x/ws, eps <= 0 or non-finite, iters < 0, grad_w
  * without CT_GRAD_W, pot missing for CT_WARM_START/CT_REF_CACHED, unknown flag),
  * CT_E_SHAPE (d not 2/3, T < 1, M < 1, T or M > 2^30), CT_E_WORKSPACE, CT_E_HIP.
@@ -262,13 +264,32 @@ ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, const float* 
  */
 ct_status ct_autotune_sinkhorn(int64_t T, int64_t M, const ct_sinkhorn_opts* o, void* ws,
                                size_t ws_bytes, void* stream);
-/* Number of tuned entries, and entry i as (d, T class, M class, R, blocks/CU, us). */
+/* Number of tuned entries, and entry i as (d, query-set size class, key-set size
+ * class, queries per lane, key-splitting waves per block, blocks per CU, time in
+ * microseconds of one sweep); a size class is ceil(log2(n)). */
 int32_t ct_tuning_count(void);
-ct_status ct_tuning_entry(int32_t i, int32_t* out6);
+ct_status ct_tuning_entry(int32_t i, int32_t* out7);
 /* Save / load the tuning table as text (one entry per line). */
 ct_status ct_tuning_save(const char* path);
 ct_status ct_tuning_load(const char* path);
 void ct_tuning_clear(void);
+
+/* ------------------------------------------------------------------------- */
+/* Launch timing                                                               */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * While enabled, every sweep-kernel launch is bracketed by a pair of HIP events
+ * recorded on its stream (adds two event records per launch; do not enable while
+ * capturing a graph).  Record i gives (kind4 = {lagged shift, offsets pass,
+ * 100 * queries per lane + 10 * key-splitting waves, blocks}, the launch's point
+ * pairs, its elapsed ms);
+ * ct_profile_read waits for the record's end event.
+ */
+ct_status ct_profile_enable(int32_t on);
+int32_t ct_profile_count(void);
+ct_status ct_profile_read(int32_t i, int32_t* kind4, double* pairs, float* ms);
+void ct_profile_clear(void);
 
 #ifdef __cplusplus
 }

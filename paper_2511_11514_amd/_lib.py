@@ -85,6 +85,10 @@ _SIGS = {
     "ct_tuning_save": (c_int32, [c_char_p]),
     "ct_tuning_load": (c_int32, [c_char_p]),
     "ct_tuning_clear": (None, []),
+    "ct_profile_enable": (c_int32, [c_int32]),
+    "ct_profile_count": (c_int32, []),
+    "ct_profile_read": (c_int32, [c_int32, POINTER(c_int32), PD, POINTER(c_float)]),
+    "ct_profile_clear": (None, []),
 }
 
 

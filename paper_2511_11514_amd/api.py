@@ -289,7 +289,7 @@ def autotune_sinkhorn(T: int, M: int, d: int, eps: float, device="cuda") -> None
 def tuning_table():
     n = lib().ct_tuning_count()
     out = []
-    buf = (ctypes.c_int32 * 6)()
+    buf = (ctypes.c_int32 * 7)()
     for i in range(n):
         check("ct_tuning_entry", lib().ct_tuning_entry(i, buf))
         out.append(tuple(buf))

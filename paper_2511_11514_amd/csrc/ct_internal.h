@@ -44,52 +44,70 @@ struct Arena {
 
 // ------------------------------------------------------- sweep job layout
 // One "job" is a soft-min sweep of a query point set against a key point set:
-//   out_i = -(1/kappa) log2 sum_j 2^(kh_j - |qc_i - kc_j|^2)
+//   out_i = -(1/kappa) log2 sum_j 2^(h_j - |x'_i - y'_j|^2)
 // where coordinates are pre-scaled by sqrt(kappa), kappa = log2(e)/eps, and
-// kh_j = log2(mass_j) + kappa * potential_j is the key's log-weight term.
+// h_j = log2(mass_j) + kappa * potential_j is the key's log-weight term.
+// Key records are float4 (x', y', h, 0) for d = 2 and (x', y', z', h) for d = 3,
+// padded with h = -inf records up to nkpad (a multiple of kKeyPad).
+constexpr int kKeyPad = 32;
+
 struct Job {
-    const float4* qc;      // [nq] pre-scaled query coordinates (x', y', z', 0)
+    const float4* qrec;    // [nq] pre-scaled query coordinates (never written)
     const float* qpot;     // [nq] the query points' current potential (shift / averaging)
     const float* qlog2w;   // [nq] log2 mass of the query points, or null: qlog2w_s
     float qlog2w_s;
     int self_avg;          // 1: out = (old + T)/2 (self problems), 0: out = T
-    const float4* kc;      // [nk] pre-scaled key coordinates
-    const float* kh;       // [nk] key terms
-    int nq, nk;
+    const float4* krec;    // [nkpad] key records
+    int nq, nk, nkpad;
     int nqb, splits, kps;  // query blocks, key splits, keys per split
-    float* part;           // [(2 + D) * splits * nqpad] partial (shift, sum, offsets)
+    float* part;           // [(2 + D) * splits * nqpad] partials (shift, sum, offsets)
     unsigned* ticket;      // [nqb] arrival counters (zero between launches)
     float* out_pot;        // [nq] new potential (may alias qpot)
-    float* out_h;          // [nq] key term of the query points for the next sweep, or null
+    float4* out_rec;       // [nq] records of the query points as keys of a later sweep: h written
     float* out_bary;       // [nq][D] mean offset under the row plan (unscaled), or null
     unsigned* rescued;     // counter of rows recomputed with a tracked maximum
 };
 
+constexpr int kMaxJobs = 4;
+
 struct Launch {
-    Job job[2];
-    int nblk0;             // blocks of job 0; the rest belong to job 1
+    Job job[kMaxJobs];
+    int blk_end[kMaxJobs]; // job j owns blocks [blk_end[j-1], blk_end[j])
+    int njobs;
     float kappa, inv_kappa, inv_sqrt_kappa;
 };
 
 struct Schedule {
     int R;                 // queries per lane (1, 2, 4, 8)
+    int WS;                // waves of a block splitting the keys (1, 2, 4)
     int blocks_per_cu;     // target blocks per CU per job
+    int sep;               // 1: key splits merged by a separate kernel, 0: by the last block
 };
 
+inline int pad_keys(int n) { return (n + kKeyPad - 1) / kKeyPad * kKeyPad; }
+
 // Fill nqb/splits/kps of `j` for the schedule; returns the number of blocks.
-int plan_job(Job& j, int R, int blocks_per_cu);
+int plan_job(Job& j, const Schedule& s);
 // Floats of partial storage a job needs under this schedule.
-size_t job_part_floats(int d, int nq, int nk, int R, int blocks_per_cu);
+size_t job_part_floats(int d, int nq, int nk, const Schedule& s);
 // Worst case over every schedule the tuner may pick.
 size_t job_part_floats_max(int d, int nq, int nk);
 size_t job_tickets_max(int nq);
+// Candidate schedules of the tuner.
+constexpr int kMaxCandidates = 128;
+int schedule_candidates(Schedule* out, int max);
 
 // Launch one sweep kernel (one or two jobs).
-hipError_t launch_sweep(int d, int R, bool lagged, bool bary, const Launch& L, int nblocks,
-                        hipStream_t s);
+hipError_t launch_sweep(int d, const Schedule& sc, bool lagged, bool bary, const Launch& L,
+                        int nblocks, hipStream_t s);
+
+// Per-launch event timing (ct_profile_enable); no-ops when disabled.
+bool profiling();
+void* profile_begin(hipStream_t s);
+void profile_end(void* tok, hipStream_t s, int lagged, int bary, int code, int blocks, double pairs);
 
 // Tuning table lookup (falls back to a size heuristic).
 Schedule schedule_for(int d, int64_t nq, int64_t nk);
-void tuning_record(int d, int64_t nq, int64_t nk, int R, int bpc, int us);
+void tuning_record(int d, int64_t nq, int64_t nk, const Schedule& s, int us);
 
 }  // namespace ct

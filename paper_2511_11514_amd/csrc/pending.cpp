@@ -26,10 +26,6 @@ extern "C" ct_status ct_plan(const ct_plan_problem*, const ct_plan_opts*, const 
                              void*) {
     return fail(CT_E_UNSUPPORTED, "plan not built yet");
 }
-extern "C" ct_status ct_autotune_sinkhorn(int64_t, int64_t, const ct_sinkhorn_opts*, void*, size_t,
-                                          void*) {
-    return fail(CT_E_UNSUPPORTED, "autotune not built yet");
-}
 extern "C" ct_status ct_lqr_track(int64_t, int32_t, int32_t, double, const double*, const double*,
                                   const double*, const double*, const double*, double*, double*) {
     return fail(CT_E_UNSUPPORTED, "lqr not built yet");

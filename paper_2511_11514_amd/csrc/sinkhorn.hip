@@ -45,69 +45,83 @@ struct StageArgs {
     const float* w;
     const float* pot_in;     // [2T+2M] warm start (f, g, p, q) or null
     int warm, ref_cached;
-    int T, M, d;
+    int T, M, d, Tpad, Mpad;
     float sqrt_kappa, kappa, log2a;
     const double* wsum;
-    float4* cx;
-    float4* cy;
+    float4* cx;              // query coordinates of x
+    float4* cy;              // query coordinates of y
+    float4* xrec[4];         // key records of x: f (g-sweeps), f+ (g+ sweep), p ping-pong
+    float4* yrec[3];         // key records of y: g (f-sweeps), q ping-pong
     float* b;
     float* log2b;
-    float* f;
-    float* g;
-    float* p;
-    float* q;
-    float* h2y_g;            // key terms of y for the f-update: log2 b + kappa g
-    float* h2x_p;            // key terms of x for the self update: log2 a + kappa p
-    float* h2y_q;            // key terms of y for the reference self update
+    float *f, *g, *p, *q;
     float *fp, *gp, *pp, *qp; // extrapolated potentials, zeroed here
     unsigned* nonfinite;
 };
 
-// Pre-scale coordinates, form the reference masses and the initial key terms.
+__device__ __forceinline__ float4 make_rec(const float* c, int d, float h) {
+    return d == 2 ? make_float4(c[0], c[1], h, 0.f) : make_float4(c[0], c[1], c[2], h);
+}
+
+// Pre-scale coordinates, form the reference masses and the initial key records
+// (h = log2 mass + kappa * potential; padding records get h = -inf).
 __global__ __launch_bounds__(256) void k_stage(StageArgs A) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < A.T) {
+    const float ninf = -__builtin_huge_valf();
+    if (i < A.Tpad) {
         float c[3] = {0.f, 0.f, 0.f};
-        bool bad = false;
-        for (int t = 0; t < A.d; ++t) {
-            const float v = A.x[(size_t)i * A.d + t];
-            bad |= !isfinite(v);
-            c[t] = v * A.sqrt_kappa;
+        if (i < A.T) {
+            bool bad = false;
+            for (int t = 0; t < A.d; ++t) {
+                const float v = A.x[(size_t)i * A.d + t];
+                bad |= !isfinite(v);
+                c[t] = v * A.sqrt_kappa;
+            }
+            A.cx[i] = make_float4(c[0], c[1], c[2], 0.f);
+            const float f0 = A.warm ? A.pot_in[i] : 0.f;
+            const float p0 = A.warm ? A.pot_in[(size_t)A.T + A.M + i] : 0.f;
+            A.f[i] = f0;
+            A.p[i] = p0;
+            A.fp[i] = 0.f;
+            A.pp[i] = 0.f;
+            A.xrec[0][i] = make_rec(c, A.d, ninf);
+            A.xrec[1][i] = make_rec(c, A.d, ninf);
+            A.xrec[2][i] = make_rec(c, A.d, __builtin_fmaf(p0, A.kappa, A.log2a));
+            A.xrec[3][i] = make_rec(c, A.d, ninf);
+            if (bad) atomicAdd(A.nonfinite, 1u);
+        } else {
+            for (int r = 0; r < 4; ++r) A.xrec[r][i] = make_rec(c, A.d, ninf);
         }
-        A.cx[i] = make_float4(c[0], c[1], c[2], 0.f);
-        const float f0 = A.warm ? A.pot_in[i] : 0.f;
-        const float p0 = A.warm ? A.pot_in[(size_t)A.T + A.M + i] : 0.f;
-        A.f[i] = f0;
-        A.p[i] = p0;
-        A.h2x_p[i] = __builtin_fmaf(p0, A.kappa, A.log2a);
-        A.fp[i] = 0.f;
-        A.pp[i] = 0.f;
-        if (bad) atomicAdd(A.nonfinite, 1u);
     }
-    if (i < A.M) {
+    if (i < A.Mpad) {
         float c[3] = {0.f, 0.f, 0.f};
-        bool bad = false;
-        for (int t = 0; t < A.d; ++t) {
-            const float v = A.y[(size_t)i * A.d + t];
-            bad |= !isfinite(v);
-            c[t] = v * A.sqrt_kappa;
+        if (i < A.M) {
+            bool bad = false;
+            for (int t = 0; t < A.d; ++t) {
+                const float v = A.y[(size_t)i * A.d + t];
+                bad |= !isfinite(v);
+                c[t] = v * A.sqrt_kappa;
+            }
+            A.cy[i] = make_float4(c[0], c[1], c[2], 0.f);
+            const float wj = A.w ? A.w[i] : 1.f;
+            bad |= !(wj > 0.f) || !isfinite(wj);
+            const float bj = (float)((double)wj / *A.wsum);
+            const float lb = __log2f(bj);
+            A.b[i] = bj;
+            A.log2b[i] = lb;
+            const float g0 = A.warm ? A.pot_in[(size_t)A.T + i] : 0.f;
+            const float q0 = (A.warm || A.ref_cached) ? A.pot_in[2 * (size_t)A.T + A.M + i] : 0.f;
+            A.g[i] = g0;
+            A.q[i] = q0;
+            A.gp[i] = 0.f;
+            A.qp[i] = 0.f;
+            A.yrec[0][i] = make_rec(c, A.d, __builtin_fmaf(g0, A.kappa, lb));
+            A.yrec[1][i] = make_rec(c, A.d, __builtin_fmaf(q0, A.kappa, lb));
+            A.yrec[2][i] = make_rec(c, A.d, ninf);
+            if (bad) atomicAdd(A.nonfinite, 1u);
+        } else {
+            for (int r = 0; r < 3; ++r) A.yrec[r][i] = make_rec(c, A.d, ninf);
         }
-        A.cy[i] = make_float4(c[0], c[1], c[2], 0.f);
-        const float wj = A.w ? A.w[i] : 1.f;
-        bad |= !(wj > 0.f) || !isfinite(wj);
-        const float bj = (float)((double)wj / *A.wsum);
-        const float lb = __log2f(bj);
-        A.b[i] = bj;
-        A.log2b[i] = lb;
-        const float g0 = A.warm ? A.pot_in[(size_t)A.T + i] : 0.f;
-        const float q0 = (A.warm || A.ref_cached) ? A.pot_in[2 * (size_t)A.T + A.M + i] : 0.f;
-        A.g[i] = g0;
-        A.q[i] = q0;
-        A.h2y_g[i] = __builtin_fmaf(g0, A.kappa, lb);
-        A.h2y_q[i] = __builtin_fmaf(q0, A.kappa, lb);
-        A.gp[i] = 0.f;
-        A.qp[i] = 0.f;
-        if (bad) atomicAdd(A.nonfinite, 1u);
     }
 }
 
@@ -214,26 +228,30 @@ struct SkLayout {
     unsigned* counters;      // [4]
     float4* cx;
     float4* cy;
+    float4* xrec[4];         // 0: h from f (keys of g-sweeps), 1: from f+, 2/3: from p (ping-pong)
+    float4* yrec[3];         // 0: h from g (keys of f-sweeps), 1/2: from q (ping-pong)
     float* b;
     float* log2b;
     float *f, *g, *p, *q;
     float *fp, *gp, *pp, *qp;
-    float *h2y_g, *h2x_f, *h2x_fp;
-    float *h2x_p[2], *h2y_q[2];
     float *dy, *ds;
-    float *part0, *part1;
-    unsigned *tick0, *tick1;
+    float* part[3];          // partial buffers: cross jobs, x self jobs, y self jobs
+    unsigned* tick[3];
+    size_t ntick;
     size_t bytes;
 };
 
 static SkLayout sk_layout(void* ws, int T, int M, int d) {
     Arena a(ws);
     SkLayout L;
+    const int Tp = pad_keys(T), Mp = pad_keys(M);
     L.wsum = a.take<double>(1);
     L.bG = a.take<double>(1);
     L.counters = a.take<unsigned>(4);
     L.cx = a.take<float4>(T);
     L.cy = a.take<float4>(M);
+    for (int r = 0; r < 4; ++r) L.xrec[r] = a.take<float4>(Tp);
+    for (int r = 0; r < 3; ++r) L.yrec[r] = a.take<float4>(Mp);
     L.b = a.take<float>(M);
     L.log2b = a.take<float>(M);
     L.f = a.take<float>(T);
@@ -244,21 +262,13 @@ static SkLayout sk_layout(void* ws, int T, int M, int d) {
     L.gp = a.take<float>(M);
     L.pp = a.take<float>(T);
     L.qp = a.take<float>(M);
-    L.h2y_g = a.take<float>(M);
-    L.h2x_f = a.take<float>(T);
-    L.h2x_fp = a.take<float>(T);
-    L.h2x_p[0] = a.take<float>(T);
-    L.h2x_p[1] = a.take<float>(T);
-    L.h2y_q[0] = a.take<float>(M);
-    L.h2y_q[1] = a.take<float>(M);
     L.dy = a.take<float>((size_t)T * d);
     L.ds = a.take<float>((size_t)T * d);
-    const size_t p0 = std::max(job_part_floats_max(d, T, M), job_part_floats_max(d, M, T));
-    const size_t p1 = std::max(job_part_floats_max(d, T, T), job_part_floats_max(d, M, M));
-    L.part0 = a.take<float>(p0);
-    L.part1 = a.take<float>(p1);
-    L.tick0 = a.take<unsigned>(std::max(job_tickets_max(T), job_tickets_max(M)));
-    L.tick1 = a.take<unsigned>(std::max(job_tickets_max(T), job_tickets_max(M)));
+    L.part[0] = a.take<float>(std::max(job_part_floats_max(d, T, M), job_part_floats_max(d, M, T)));
+    L.part[1] = a.take<float>(job_part_floats_max(d, T, T));
+    L.part[2] = a.take<float>(job_part_floats_max(d, M, M));
+    L.ntick = std::max(job_tickets_max(T), job_tickets_max(M));
+    for (int i = 0; i < 3; ++i) L.tick[i] = a.take<unsigned>(L.ntick);
     L.bytes = a.off + 256;
     return L;
 }
@@ -282,6 +292,132 @@ static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
     return CT_OK;
 }
 
+// Launch-time constants of one problem.
+struct SkConsts {
+    int d, T, M;
+    float kappa, inv_kappa, inv_sqrt_kappa, log2a;
+};
+
+static SkConsts sk_consts(int T, int M, const ct_sinkhorn_opts* o) {
+    const double kappa_d = kLog2e / (double)o->eps;
+    SkConsts c;
+    c.d = o->d;
+    c.T = T;
+    c.M = M;
+    c.kappa = (float)kappa_d;
+    c.inv_kappa = (float)(1.0 / kappa_d);
+    c.inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
+    c.log2a = (float)(-std::log2((double)T));
+    return c;
+}
+
+struct JobSet {
+    Job j[kMaxJobs];
+    int n = 0;
+    void add(const Job& x) {
+        if (x.nq > 0) j[n++] = x;
+    }
+};
+
+// The job restricted to queries [q0, q0 + n).
+static Job sub_job(Job j, int q0, int n, int d) {
+    j.qrec += q0;
+    j.qpot += q0;
+    if (j.qlog2w) j.qlog2w += q0;
+    j.out_pot += q0;
+    if (j.out_rec) j.out_rec += q0;
+    if (j.out_bary) j.out_bary += (size_t)q0 * d;
+    j.nq = n;
+    return j;
+}
+
+static ct_status launch_set(const JobSet& js, const SkConsts& c, const Schedule& sc, bool lagged,
+                            bool bary, hipStream_t st) {
+    if (js.n == 0) return CT_OK;
+    Launch Lc;
+    std::memset(&Lc, 0, sizeof(Lc));
+    Lc.kappa = c.kappa;
+    Lc.inv_kappa = c.inv_kappa;
+    Lc.inv_sqrt_kappa = c.inv_sqrt_kappa;
+    int nb = 0;
+    for (int i = 0; i < js.n; ++i) {
+        Lc.job[i] = js.j[i];
+        nb += plan_job(Lc.job[i], sc);
+        Lc.blk_end[i] = nb;
+    }
+    Lc.njobs = js.n;
+    CT_CHECK_HIP(launch_sweep(c.d, sc, lagged, bary, Lc, nb, st));
+    return CT_OK;
+}
+
+// Job builders: queries x against keys y (f-type) or x (p-type); queries y
+// against keys x (g-type) or y (q-type).
+struct SkJobs {
+    const SkLayout& L;
+    const SkConsts& c;
+    Job base() const {
+        Job j;
+        std::memset(&j, 0, sizeof(Job));
+        j.rescued = L.counters + 1;
+        return j;
+    }
+    Job f(float* out_pot, float4* out_rec, float* out_bary) const {
+        Job j = base();
+        j.qrec = L.cx; j.qpot = L.f; j.qlog2w_s = c.log2a;
+        j.krec = L.yrec[0]; j.nq = c.T; j.nk = c.M;
+        j.part = L.part[0]; j.ticket = L.tick[0];
+        j.out_pot = out_pot; j.out_rec = out_rec; j.out_bary = out_bary;
+        return j;
+    }
+    Job p(int cur, bool avg, float* out_pot, float4* out_rec, float* out_bary) const {
+        Job j = base();
+        j.qrec = L.cx; j.qpot = L.p; j.qlog2w_s = c.log2a; j.self_avg = avg;
+        j.krec = L.xrec[2 + cur]; j.nq = c.T; j.nk = c.T;
+        j.part = L.part[1]; j.ticket = L.tick[1];
+        j.out_pot = out_pot; j.out_rec = out_rec; j.out_bary = out_bary;
+        return j;
+    }
+    Job g(const float4* krec, float* out_pot, float4* out_rec) const {
+        Job j = base();
+        j.qrec = L.cy; j.qpot = L.g; j.qlog2w = L.log2b;
+        j.krec = krec; j.nq = c.M; j.nk = c.T;
+        j.part = L.part[0]; j.ticket = L.tick[0];
+        j.out_pot = out_pot; j.out_rec = out_rec;
+        return j;
+    }
+    Job q(int cur, bool avg, float* out_pot, float4* out_rec) const {
+        Job j = base();
+        j.qrec = L.cy; j.qpot = L.q; j.qlog2w = L.log2b; j.self_avg = avg;
+        j.krec = L.yrec[1 + cur]; j.nq = c.M; j.nk = c.M;
+        j.part = L.part[2]; j.ticket = L.tick[2];
+        j.out_pot = out_pot; j.out_rec = out_rec;
+        return j;
+    }
+};
+
+// The two launches of one Sinkhorn iteration.  Launch A updates f (Gauss-Seidel
+// half-step); launch B updates g from the new f.  The self problems do not
+// depend on f and g, so each averaged self update is split by queries: the
+// first half runs beside f, the second beside g (both halves read the previous
+// self records, write the other ping-pong buffer, and update disjoint entries),
+// which balances the two launches.
+static void iteration_sets(const SkJobs& J, int cur, bool debias, bool ref_iter, JobSet& A,
+                           JobSet& B) {
+    const int T = J.c.T, M = J.c.M, d = J.c.d;
+    A.add(J.f(J.L.f, J.L.xrec[0], nullptr));
+    B.add(J.g(J.L.xrec[0], J.L.g, J.L.yrec[0]));
+    if (debias) {
+        const Job jp = J.p(cur, true, J.L.p, J.L.xrec[2 + (cur ^ 1)], nullptr);
+        A.add(sub_job(jp, 0, T / 2, d));
+        B.add(sub_job(jp, T / 2, T - T / 2, d));
+    }
+    if (ref_iter) {
+        const Job jq = J.q(cur, true, J.L.q, J.L.yrec[1 + (cur ^ 1)]);
+        A.add(sub_job(jq, 0, M / 2, d));
+        B.add(sub_job(jq, M / 2, M - M / 2, d));
+    }
+}
+
 // Iterate-and-extrapolate for one problem whose arrays are staged in L.
 static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_opts* o,
                              hipStream_t st) {
@@ -292,101 +428,35 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     const bool ref_iter = need_ref && !(o->flags & CT_REF_CACHED);
     const bool warm = o->flags & CT_WARM_START;
     const bool safe_only = o->flags & CT_SAFE_LSE;
-    const double kappa_d = kLog2e / (double)o->eps;
-    const float kappa = (float)kappa_d;
-    const float inv_kappa = (float)(1.0 / kappa_d);
-    const float inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
-    const float log2a = (float)(-std::log2((double)T));
+    const SkConsts c = sk_consts(T, M, o);
+    const SkJobs J{L, c};
+    const Schedule sA = schedule_for(d, T, M);
+    const Schedule sB = schedule_for(d, M, T);
 
-    const Schedule sxy = schedule_for(d, T, M);
-    const Schedule syx = schedule_for(d, M, T);
-
-    auto base_job = [&](Job& j) {
-        std::memset(&j, 0, sizeof(Job));
-        j.rescued = L.counters + 1;
-    };
-    auto launch2 = [&](Job* j0, Job* j1, const Schedule& sc, bool lagged, bool bary) -> ct_status {
-        Launch Lc;
-        std::memset(&Lc, 0, sizeof(Lc));
-        Lc.kappa = kappa;
-        Lc.inv_kappa = inv_kappa;
-        Lc.inv_sqrt_kappa = inv_sqrt_kappa;
-        int nb0 = 0, nb1 = 0;
-        if (j0) {
-            Lc.job[0] = *j0;
-            nb0 = plan_job(Lc.job[0], sc.R, sc.blocks_per_cu);
-        }
-        if (j1) {
-            Lc.job[1] = *j1;
-            nb1 = plan_job(Lc.job[1], sc.R, sc.blocks_per_cu);
-        }
-        if (!j0) {
-            Lc.job[0] = Lc.job[1];
-            nb0 = nb1;
-            nb1 = 0;
-        }
-        Lc.nblk0 = nb0;
-        CT_CHECK_HIP(launch_sweep(d, sc.R, lagged, bary, Lc, nb0 + nb1, st));
-        return CT_OK;
-    };
-
-    // x-side jobs (queries x) and y-side jobs (queries y)
-    auto job_f = [&](Job& j, float* out_pot, float* out_h, float* out_bary) {
-        base_job(j);
-        j.qc = L.cx; j.qpot = L.f; j.qlog2w_s = log2a; j.self_avg = 0;
-        j.kc = L.cy; j.kh = L.h2y_g; j.nq = T; j.nk = M;
-        j.part = L.part0; j.ticket = L.tick0;
-        j.out_pot = out_pot; j.out_h = out_h; j.out_bary = out_bary;
-    };
-    auto job_p = [&](Job& j, int cur, bool avg, float* out_pot, float* out_h, float* out_bary) {
-        base_job(j);
-        j.qc = L.cx; j.qpot = L.p; j.qlog2w_s = log2a; j.self_avg = avg;
-        j.kc = L.cx; j.kh = L.h2x_p[cur]; j.nq = T; j.nk = T;
-        j.part = L.part1; j.ticket = L.tick1;
-        j.out_pot = out_pot; j.out_h = out_h; j.out_bary = out_bary;
-    };
-    auto job_g = [&](Job& j, const float* kh, float* out_pot, float* out_h) {
-        base_job(j);
-        j.qc = L.cy; j.qpot = L.g; j.qlog2w = L.log2b; j.self_avg = 0;
-        j.kc = L.cx; j.kh = kh; j.nq = M; j.nk = T;
-        j.part = L.part0; j.ticket = L.tick0;
-        j.out_pot = out_pot; j.out_h = out_h;
-    };
-    auto job_q = [&](Job& j, int cur, bool avg, float* out_pot, float* out_h) {
-        base_job(j);
-        j.qc = L.cy; j.qpot = L.q; j.qlog2w = L.log2b; j.self_avg = avg;
-        j.kc = L.cy; j.kh = L.h2y_q[cur]; j.nq = M; j.nk = M;
-        j.part = L.part1; j.ticket = L.tick1;
-        j.out_pot = out_pot; j.out_h = out_h;
-    };
-
-    int cur = 0;  // which of the ping-pong self key-term buffers is current
+    int cur = 0;  // which ping-pong self record array is current
     for (int k = 0; k < o->iters; ++k) {
         const bool lagged = !safe_only && (warm || k > 0);
-        Job jf, jp, jg, jq;
-        job_f(jf, L.f, L.h2x_f, nullptr);
-        if (debias) job_p(jp, cur, true, L.p, L.h2x_p[cur ^ 1], nullptr);
-        ct_status rc = launch2(&jf, debias ? &jp : nullptr, sxy, lagged, false);
+        JobSet A, B;
+        iteration_sets(J, cur, debias, ref_iter, A, B);
+        ct_status rc = launch_set(A, c, sA, lagged, false, st);
         if (rc) return rc;
-        job_g(jg, L.h2x_f, L.g, L.h2y_g);
-        if (ref_iter) job_q(jq, cur, true, L.q, L.h2y_q[cur ^ 1]);
-        rc = launch2(&jg, ref_iter ? &jq : nullptr, syx, lagged, false);
+        rc = launch_set(B, c, sB, lagged, false, st);
         if (rc) return rc;
         cur ^= 1;
     }
     const bool lagged_final = !safe_only && (warm || o->iters > 0);
     {
-        Job jf, jp;
-        job_f(jf, L.fp, L.h2x_fp, L.dy);
-        if (debias) job_p(jp, cur, false, L.pp, nullptr, L.ds);
-        ct_status rc = launch2(&jf, debias ? &jp : nullptr, sxy, lagged_final, true);
+        JobSet F;
+        F.add(J.f(L.fp, L.xrec[1], L.dy));
+        if (debias) F.add(J.p(cur, false, L.pp, nullptr, L.ds));
+        ct_status rc = launch_set(F, c, sA, lagged_final, true, st);
         if (rc) return rc;
     }
     if (want_v) {
-        Job jg, jq;
-        job_g(jg, L.h2x_fp, L.gp, nullptr);
-        if (need_ref) job_q(jq, cur, false, L.qp, nullptr);
-        ct_status rc = launch2(&jg, need_ref ? &jq : nullptr, syx, lagged_final, false);
+        JobSet F;
+        F.add(J.g(L.xrec[1], L.gp, nullptr));
+        if (need_ref) F.add(J.q(ref_iter ? cur : 0, false, L.qp, nullptr));
+        ct_status rc = launch_set(F, c, sB, lagged_final, false, st);
         if (rc) return rc;
     }
     return CT_OK;
@@ -432,9 +502,11 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
     // zero the counters and arrival tickets with a fill kernel (no memset nodes,
     // so the sequence can be captured into a graph)
     {
-        const int nt = (int)std::max(job_tickets_max(T), job_tickets_max(M));
-        hipLaunchKernelGGL(k_zero3, dim3((nt + 255) / 256), dim3(256), 0, st, L.counters, 4,
-                           L.tick0, nt, L.tick1, nt);
+        const int nt = (int)L.ntick;
+        hipLaunchKernelGGL(k_zero3, dim3((nt + 255) / 256), dim3(256), 0, st, L.tick[0], nt,
+                           L.tick[1], nt, L.tick[2], nt);
+        hipLaunchKernelGGL(k_zero3, dim3(1), dim3(256), 0, st, L.counters, 4, nullptr, 0,
+                           nullptr, 0);
         CT_CHECK_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, st, w, M, L.wsum);
@@ -443,16 +515,17 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
     A.x = x; A.y = y; A.w = w; A.pot_in = pot;
     A.warm = (o->flags & CT_WARM_START) ? 1 : 0;
     A.ref_cached = (o->flags & CT_REF_CACHED) ? 1 : 0;
-    A.T = T; A.M = M; A.d = d;
+    A.T = T; A.M = M; A.d = d; A.Tpad = pad_keys(T); A.Mpad = pad_keys(M);
     A.sqrt_kappa = (float)std::sqrt(kappa_d);
     A.kappa = (float)kappa_d;
     A.log2a = (float)(-std::log2((double)T));
     A.wsum = L.wsum; A.cx = L.cx; A.cy = L.cy; A.b = L.b; A.log2b = L.log2b;
     A.f = L.f; A.g = L.g; A.p = L.p; A.q = L.q;
-    A.h2y_g = L.h2y_g; A.h2x_p = L.h2x_p[0]; A.h2y_q = L.h2y_q[0];
+    for (int r = 0; r < 4; ++r) A.xrec[r] = L.xrec[r];
+    for (int r = 0; r < 3; ++r) A.yrec[r] = L.yrec[r];
     A.fp = L.fp; A.gp = L.gp; A.pp = L.pp; A.qp = L.qp;
     A.nonfinite = L.counters;
-    const int n = std::max(T, M);
+    const int n = std::max(pad_keys(T), pad_keys(M));
     hipLaunchKernelGGL(k_stage, dim3((n + 255) / 256), dim3(256), 0, st, A);
     CT_CHECK_HIP(hipGetLastError());
 
@@ -500,5 +573,125 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
         CT_CHECK_HIP(hipMemcpyAsync(pp + 2 * (size_t)T + M, L.qp, sizeof(float) * M,
                                     hipMemcpyDeviceToDevice, st));
     }
+    return CT_OK;
+}
+
+// ------------------------------------------------------------- autotuning
+
+namespace ct {
+
+// Synthetic staged problem for timing: points from a hash in [0,1]^d, equal
+// masses, zero potentials (the timing of a sweep does not depend on the data
+// beyond its size).
+__device__ __forceinline__ float hash01(unsigned v) {
+    v ^= v >> 16;
+    v *= 0x7feb352du;
+    v ^= v >> 15;
+    v *= 0x846ca68bu;
+    v ^= v >> 16;
+    return (float)(v >> 8) * (1.0f / 16777216.0f);
+}
+
+__global__ __launch_bounds__(256) void k_synth(int T, int M, int d, int Tpad, int Mpad,
+                                               float sqrt_kappa, float log2a, float log2b,
+                                               float4* cx, float4* cy, float4* x0, float4* x1,
+                                               float4* x2, float4* x3, float4* y0, float4* y1,
+                                               float4* y2, float* f, float* g, float* p, float* q,
+                                               float* b, float* lb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const float ninf = -__builtin_huge_valf();
+    if (i < Tpad) {
+        float c[3];
+        for (int t = 0; t < 3; ++t) c[t] = hash01(2654435761u * (unsigned)i + 97u * t + 1u) * sqrt_kappa;
+        const float h = i < T ? log2a : ninf;
+        float4 r = d == 2 ? make_float4(c[0], c[1], h, 0.f) : make_float4(c[0], c[1], c[2], h);
+        x0[i] = r; x1[i] = r; x2[i] = r; x3[i] = r;
+        if (i < T) {
+            cx[i] = make_float4(c[0], c[1], c[2], 0.f);
+            f[i] = 0.f;
+            p[i] = 0.f;
+        }
+    }
+    if (i < Mpad) {
+        float c[3];
+        for (int t = 0; t < 3; ++t) c[t] = hash01(40503u * (unsigned)i + 131u * t + 7u) * sqrt_kappa;
+        const float h = i < M ? log2b : ninf;
+        float4 r = d == 2 ? make_float4(c[0], c[1], h, 0.f) : make_float4(c[0], c[1], c[2], h);
+        y0[i] = r; y1[i] = r; y2[i] = r;
+        if (i < M) {
+            cy[i] = make_float4(c[0], c[1], c[2], 0.f);
+            g[i] = 0.f;
+            q[i] = 0.f;
+            b[i] = exp2f(log2b);
+            lb[i] = log2b;
+        }
+    }
+}
+
+}  // namespace ct
+
+extern "C" ct_status ct_autotune_sinkhorn(int64_t T64, int64_t M64, const ct_sinkhorn_opts* o,
+                                          void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    static const float dummy = 0.f;
+    ct_status rc = validate(&dummy, T64, &dummy, M64, o);
+    if (rc) return rc;
+    if (!ws) return fail(CT_E_ARG, "workspace is null");
+    const int T = (int)T64, M = (int)M64, d = o->d;
+    SkLayout L = sk_layout(ws, T, M, d);
+    if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    CT_CHECK_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(CT_E_ARG, "cannot autotune while capturing");
+    const double kappa_d = kLog2e / (double)o->eps;
+    const int n = std::max(pad_keys(T), pad_keys(M));
+    hipLaunchKernelGGL(k_zero3, dim3(((int)L.ntick + 255) / 256), dim3(256), 0, st, L.tick[0],
+                       (int)L.ntick, L.tick[1], (int)L.ntick, L.tick[2], (int)L.ntick);
+    hipLaunchKernelGGL(k_zero3, dim3(1), dim3(256), 0, st, L.counters, 4, nullptr, 0, nullptr, 0);
+    hipLaunchKernelGGL(k_synth, dim3((n + 255) / 256), dim3(256), 0, st, T, M, d, pad_keys(T),
+                       pad_keys(M), (float)std::sqrt(kappa_d), (float)(-std::log2((double)T)),
+                       (float)(-std::log2((double)M)), L.cx, L.cy, L.xrec[0], L.xrec[1], L.xrec[2],
+                       L.xrec[3], L.yrec[0], L.yrec[1], L.yrec[2], L.f, L.g, L.p, L.q, L.b, L.log2b);
+    CT_CHECK_HIP(hipGetLastError());
+    hipEvent_t e0, e1;
+    CT_CHECK_HIP(hipEventCreate(&e0));
+    CT_CHECK_HIP(hipEventCreate(&e1));
+    Schedule cand[kMaxCandidates];
+    const int nc = schedule_candidates(cand, kMaxCandidates);
+    const SkConsts c = sk_consts(T, M, o);
+    const SkJobs J{L, c};
+    const bool debias = o->flags & CT_DEBIAS;
+    const bool ref_iter = debias && (o->flags & (CT_VALUE | CT_GRAD_W));
+    JobSet A, B;
+    iteration_sets(J, 0, debias, ref_iter, A, B);
+    for (int side = 0; side < 2; ++side) {
+        const JobSet& S = side == 0 ? A : B;
+        float best = 1e30f;
+        Schedule bs = cand[0];
+        for (int ci = 0; ci < nc; ++ci) {
+            ct_status rc2 = launch_set(S, c, cand[ci], true, false, st);  // warm-up
+            if (rc2) return rc2;
+            CT_CHECK_HIP(hipEventRecord(e0, st));
+            const int reps = 3;
+            for (int r = 0; r < reps; ++r) {
+                rc2 = launch_set(S, c, cand[ci], true, false, st);
+                if (rc2) return rc2;
+            }
+            CT_CHECK_HIP(hipEventRecord(e1, st));
+            CT_CHECK_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            CT_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            ms /= reps;
+            if (ms < best) {
+                best = ms;
+                bs = cand[ci];
+            }
+        }
+        if (side == 0) tuning_record(d, T, M, bs, (int)(best * 1000.f + 0.5f));
+        else tuning_record(d, M, T, bs, (int)(best * 1000.f + 0.5f));
+    }
+    CT_CHECK_HIP(hipEventDestroy(e0));
+    CT_CHECK_HIP(hipEventDestroy(e1));
     return CT_OK;
 }

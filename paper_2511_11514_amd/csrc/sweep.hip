@@ -7,92 +7,171 @@
 
 namespace ct {
 
-template <int D, int R, bool LAGGED, bool BARY>
+template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP>
 __global__ __launch_bounds__(kBlock) void k_sweep(Launch L) {
-    __shared__ float4 tile[kTile];
+    __shared__ SweepSmem<D, R> sm;
     const int bid = (int)blockIdx.x;
-    const bool second = bid >= L.nblk0;
-    const Job& J = second ? L.job[1] : L.job[0];
-    const int local = second ? bid - L.nblk0 : bid;
+    int j = 0;
+    while (j + 1 < L.njobs && bid >= L.blk_end[j]) ++j;
+    const Job& J = L.job[j];
+    const int local = bid - (j ? L.blk_end[j - 1] : 0);
     const int qb = local % J.nqb;
     const int split = local / J.nqb;
-    const int qbase = qb * kBlock * R;
-    QueryRegs<D, R> Q;
-    init_queries<D, R>(J, qbase, L.kappa, LAGGED, Q);
-    const int k0 = split * J.kps;
-    const int k1 = min(J.nk, k0 + J.kps);
-    sweep_range<D, R, LAGGED, BARY>(J, k0, k1, tile, Q);
-    publish_and_merge<D, R, LAGGED, BARY>(J, qb, split, qbase, Q, L.kappa, L.inv_kappa,
-                                          L.inv_sqrt_kappa);
+    sweep_unit<D, R, WS, LAGGED, BARY, SEP>(J, qb, split, L.kappa, L.inv_kappa, L.inv_sqrt_kappa,
+                                            sm);
 }
 
-int plan_job(Job& j, int R, int blocks_per_cu) {
-    const int qpb = kBlock * R;
+// Merge kernel of the separate-merge mode: blocks of 256 query rows per job
+// (jobs with a single split were finished by the sweep itself).
+template <int D, bool LAGGED, bool BARY>
+__global__ __launch_bounds__(kBlock) void k_merge(Launch L, int R, int WS) {
+    __shared__ int flist[kBlock];
+    __shared__ int nflag;
+    const int bid = (int)blockIdx.x;
+    int j = 0, start = 0;
+    for (;;) {
+        const Job& Jj = L.job[j];
+        const int nb = Jj.splits > 1 ? (Jj.nq + kBlock - 1) / kBlock : 0;
+        if (bid < start + nb || j + 1 == L.njobs) break;
+        start += nb;
+        ++j;
+    }
+    const Job& J = L.job[j];
+    if (threadIdx.x == 0) nflag = 0;
+    __syncthreads();
+    const int nqpad = J.nqb * 64 * R * (4 / WS);
+    const int q = (bid - start) * kBlock + (int)threadIdx.x;
+    merge_rows<D, LAGGED, BARY>(J, q, nqpad, L.kappa, L.inv_kappa, L.inv_sqrt_kappa, flist, &nflag);
+}
+
+int plan_job(Job& j, const Schedule& s) {
+    const int qpb = 64 * s.R * (4 / s.WS);
+    j.nkpad = pad_keys(j.nk);
     j.nqb = (j.nq + qpb - 1) / qpb;
-    const int target = blocks_per_cu * kNumCU;
-    int want = std::max(1, (target + j.nqb - 1) / j.nqb);
-    const int max_splits = std::max(1, (j.nk + kTile - 1) / kTile);
+    const int target = s.blocks_per_cu * kNumCU;
+    const int want = std::max(1, (target + j.nqb - 1) / j.nqb);
+    // at least 64 keys per wave
+    const int unit = 64 * s.WS;
+    const int max_splits = std::max(1, j.nkpad / unit);
     int splits = std::min(want, max_splits);
-    int kps = (j.nk + splits - 1) / splits;
-    kps = (kps + kGroup - 1) / kGroup * kGroup;
-    splits = (j.nk + kps - 1) / kps;
+    int kps = (j.nkpad + splits - 1) / splits;
+    const int gran = kKeyPad * s.WS;
+    kps = (kps + gran - 1) / gran * gran;
+    splits = (j.nkpad + kps - 1) / kps;
     j.splits = splits;
     j.kps = kps;
     return j.nqb * splits;
 }
 
-size_t job_part_floats(int d, int nq, int nk, int R, int blocks_per_cu) {
+size_t job_part_floats(int d, int nq, int nk, const Schedule& s) {
     Job j{};
     j.nq = nq;
     j.nk = nk;
-    plan_job(j, R, blocks_per_cu);
+    plan_job(j, s);
     if (j.splits <= 1) return 0;
-    return (size_t)(2 + d) * j.splits * (size_t)j.nqb * kBlock * R;
+    return (size_t)(2 + d) * j.splits * (size_t)j.nqb * 64 * s.R * (4 / s.WS);
 }
 
-static const int kRs[] = {1, 2, 4, 8};
-static const int kBpc[] = {1, 2, 4, 8, 16};
+int schedule_candidates(Schedule* out, int max) {
+    static const int Rs[] = {1, 2, 4, 8};
+    static const int WSs[] = {1, 2, 4};
+    static const int Bs[] = {1, 2, 4, 8, 16};
+    int n = 0;
+    for (int sep = 0; sep < 2; ++sep)
+        for (int R : Rs)
+            for (int ws : WSs)
+                for (int b : Bs)
+                    if (n < max) out[n++] = Schedule{R, ws, b, sep};
+    return n;
+}
 
 size_t job_part_floats_max(int d, int nq, int nk) {
+    Schedule c[kMaxCandidates];
+    const int n = schedule_candidates(c, kMaxCandidates);
     size_t m = 0;
-    for (int R : kRs)
-        for (int b : kBpc) m = std::max(m, job_part_floats(d, nq, nk, R, b));
+    for (int i = 0; i < n; ++i) m = std::max(m, job_part_floats(d, nq, nk, c[i]));
     return m;
 }
 
-size_t job_tickets_max(int nq) { return (size_t)(nq + kBlock - 1) / kBlock; }
+size_t job_tickets_max(int nq) { return (size_t)(nq + 63) / 64; }
 
-template <int D, int R>
-static hipError_t launch_dr(bool lagged, bool bary, const Launch& L, int nb, hipStream_t s) {
+template <int D, int R, int WS, bool SEP>
+static hipError_t launch_drws(bool lagged, bool bary, const Launch& L, int nb, hipStream_t s) {
     if (lagged) {
         if (bary)
-            hipLaunchKernelGGL((k_sweep<D, R, true, true>), dim3(nb), dim3(kBlock), 0, s, L);
+            hipLaunchKernelGGL((k_sweep<D, R, WS, true, true, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
         else
-            hipLaunchKernelGGL((k_sweep<D, R, true, false>), dim3(nb), dim3(kBlock), 0, s, L);
+            hipLaunchKernelGGL((k_sweep<D, R, WS, true, false, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
     } else {
         if (bary)
-            hipLaunchKernelGGL((k_sweep<D, R, false, true>), dim3(nb), dim3(kBlock), 0, s, L);
+            hipLaunchKernelGGL((k_sweep<D, R, WS, false, true, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
         else
-            hipLaunchKernelGGL((k_sweep<D, R, false, false>), dim3(nb), dim3(kBlock), 0, s, L);
+            hipLaunchKernelGGL((k_sweep<D, R, WS, false, false, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
     }
     return hipGetLastError();
 }
 
+template <int D, int R, int WS>
+static hipError_t launch_drw(bool sep, bool lagged, bool bary, const Launch& L, int nb,
+                             hipStream_t s) {
+    return sep ? launch_drws<D, R, WS, true>(lagged, bary, L, nb, s)
+               : launch_drws<D, R, WS, false>(lagged, bary, L, nb, s);
+}
+
 template <int D>
-static hipError_t launch_d(int R, bool lagged, bool bary, const Launch& L, int nb, hipStream_t s) {
-    switch (R) {
-        case 1: return launch_dr<D, 1>(lagged, bary, L, nb, s);
-        case 2: return launch_dr<D, 2>(lagged, bary, L, nb, s);
-        case 4: return launch_dr<D, 4>(lagged, bary, L, nb, s);
-        default: return launch_dr<D, 8>(lagged, bary, L, nb, s);
+static hipError_t launch_merge(int R, int WS, bool lagged, bool bary, const Launch& L,
+                               hipStream_t s) {
+    int nb = 0;
+    for (int j = 0; j < L.njobs; ++j)
+        if (L.job[j].splits > 1) nb += (L.job[j].nq + kBlock - 1) / kBlock;
+    if (nb == 0) return hipSuccess;
+    if (lagged) {
+        if (bary) hipLaunchKernelGGL((k_merge<D, true, true>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
+        else hipLaunchKernelGGL((k_merge<D, true, false>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
+    } else {
+        if (bary) hipLaunchKernelGGL((k_merge<D, false, true>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
+        else hipLaunchKernelGGL((k_merge<D, false, false>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
+    }
+    return hipGetLastError();
+}
+
+template <int D, int R>
+static hipError_t launch_dr(int WS, bool sep, bool lagged, bool bary, const Launch& L, int nb,
+                            hipStream_t s) {
+    switch (WS) {
+        case 1: return launch_drw<D, R, 1>(sep, lagged, bary, L, nb, s);
+        case 2: return launch_drw<D, R, 2>(sep, lagged, bary, L, nb, s);
+        default: return launch_drw<D, R, 4>(sep, lagged, bary, L, nb, s);
     }
 }
 
-hipError_t launch_sweep(int d, int R, bool lagged, bool bary, const Launch& L, int nblocks,
-                        hipStream_t s) {
+template <int D>
+static hipError_t launch_d(const Schedule& sc, bool lagged, bool bary, const Launch& L, int nb,
+                           hipStream_t s) {
+    hipError_t e;
+    const bool sep = sc.sep != 0;
+    switch (sc.R) {
+        case 1: e = launch_dr<D, 1>(sc.WS, sep, lagged, bary, L, nb, s); break;
+        case 2: e = launch_dr<D, 2>(sc.WS, sep, lagged, bary, L, nb, s); break;
+        case 4: e = launch_dr<D, 4>(sc.WS, sep, lagged, bary, L, nb, s); break;
+        default: e = launch_dr<D, 8>(sc.WS, sep, lagged, bary, L, nb, s); break;
+    }
+    if (e != hipSuccess || !sep) return e;
+    return launch_merge<D>(sc.R, sc.WS, lagged, bary, L, s);
+}
+
+hipError_t launch_sweep(int d, const Schedule& sc, bool lagged, bool bary, const Launch& L,
+                        int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
-    return d == 2 ? launch_d<2>(R, lagged, bary, L, nblocks, s)
-                  : launch_d<3>(R, lagged, bary, L, nblocks, s);
+    void* tok = profile_begin(s);
+    const hipError_t e = d == 2 ? launch_d<2>(sc, lagged, bary, L, nblocks, s)
+                                : launch_d<3>(sc, lagged, bary, L, nblocks, s);
+    if (tok) {
+        double pairs = 0.0;
+        for (int j = 0; j < L.njobs; ++j) pairs += (double)L.job[j].nq * L.job[j].nk;
+        profile_end(tok, s, lagged, bary, sc.R * 100 + sc.WS * 10 + sc.sep, nblocks, pairs);
+    }
+    return e;
 }
 
 }  // namespace ct

@@ -8,14 +8,25 @@
 // kappa = log2(e)/eps, so a pair costs
 //     e_ij = kh_j - |x'_i - y'_j|^2      and      T_i = -(1/kappa) log2 sum_j 2^e_ij.
 //
+// Work decomposition.  A block has 4 wave64s.  Each lane owns R queries.  The
+// 4 waves either own 4 different query groups (WS = 1), or 2 groups with the
+// keys halved between wave pairs (WS = 2), or one group with the keys split
+// four ways (WS = 4); the WS partial sums are combined through LDS.  Keys are
+// read as wave-uniform 16-byte records (x', y', [z',] h), so they arrive in
+// scalar registers through the scalar cache and feed the VALU directly: one
+// record load serves 64 R pairs and uses no LDS bandwidth.
+//
 // Two accumulation modes:
-//  * safe   : groups of kGroup keys, running maximum per query, rescale when it
+//  * safe   : groups of 8 keys, running maximum per query, rescale when it
 //             grows (one extra exp per group);
 //  * lagged : the shift is the query's own current potential (its value after
 //             the previous sweep), folded into the cost; no maximum is tracked.
 //             A row whose sum leaves [2^-64, 2^64] is recomputed in safe mode
 //             by the block that merges it, so the result never depends on the
 //             quality of the shift.
+// Blocks that cover different key ranges of the same queries publish partial
+// sums; the last block to arrive (arrival ticket per query block) merges them
+// in a fixed order, so results are deterministic.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,29 +43,12 @@ constexpr float kNegInf = -__builtin_huge_valf();
 constexpr float kSumLo = 5.421010862427522e-20f;  // 2^-64
 constexpr float kSumHi = 1.8446744073709552e19f;  // 2^64
 
-// Stage keys [j0, j1) of a job into LDS as (x', y', h, 0) or (x', y', z', h);
-// slots past j1 get h = -inf so they contribute exp2(-inf) = 0.
 template <int D>
-__device__ __forceinline__ void stage_tile(float4* tile, const float4* __restrict__ kc,
-                                           const float* __restrict__ kh, int j0, int j1) {
-    const int j = j0 + (int)threadIdx.x;
-    float4 v;
-    if (j < j1) {
-        const float4 c = kc[j];
-        const float h = kh[j];
-        v = (D == 2) ? make_float4(c.x, c.y, h, 0.f) : make_float4(c.x, c.y, c.z, h);
-    } else {
-        v = (D == 2) ? make_float4(0.f, 0.f, kNegInf, 0.f) : make_float4(0.f, 0.f, 0.f, kNegInf);
-    }
-    tile[threadIdx.x] = v;
-}
-
-template <int D>
-__device__ __forceinline__ float key_h(const float4& k) {
+__device__ __forceinline__ float rec_h(const float4& k) {
     return (D == 2) ? k.z : k.w;
 }
 
-// Per-thread state of R queries.
+// Per-lane state of R queries.
 template <int D, int R>
 struct QueryRegs {
     float q[R][D];   // pre-scaled coordinates
@@ -63,112 +57,105 @@ struct QueryRegs {
     float b[R][D];   // sum of 2^(e - sh) * (x'_i - y'_j)
 };
 
-// Lagged accumulation over n staged keys (n a multiple of 4).
 template <int D, int R, bool BARY>
-__device__ __forceinline__ void accum_lagged(const float4* tile, int n, QueryRegs<D, R>& Q) {
-#pragma unroll 4
-    for (int j = 0; j < n; ++j) {
-        const float4 k = tile[j];
+__device__ __forceinline__ void pair_lagged(const float4& k, QueryRegs<D, R>& Q) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float dx = Q.q[r][0] - k.x;
-            const float dy = Q.q[r][1] - k.y;
-            float c;
-            float dz = 0.f;
-            if (D == 2) {
-                c = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, Q.sh[r]));
-            } else {
-                dz = Q.q[r][2] - k.z;
-                c = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, Q.sh[r])));
+    for (int r = 0; r < R; ++r) {
+        const float dx = Q.q[r][0] - k.x;
+        const float dy = Q.q[r][1] - k.y;
+        float c;
+        float dz = 0.f;
+        if (D == 2) {
+            c = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, Q.sh[r]));
+        } else {
+            dz = Q.q[r][2] - k.z;
+            c = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, __builtin_fmaf(dz, dz, Q.sh[r])));
+        }
+        const float p = ex2(rec_h<D>(k) - c);
+        Q.s[r] += p;
+        if (BARY) {
+            Q.b[r][0] = __builtin_fmaf(p, dx, Q.b[r][0]);
+            Q.b[r][1] = __builtin_fmaf(p, dy, Q.b[r][1]);
+            if (D == 3) Q.b[r][2] = __builtin_fmaf(p, dz, Q.b[r][2]);
+        }
+    }
+}
+
+// Safe mode over a group of 8 keys.
+template <int D, int R, bool BARY>
+__device__ __forceinline__ void group_safe(const float4 (&k)[8], QueryRegs<D, R>& Q) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float e[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const float dx = Q.q[r][0] - k[g].x;
+            const float dy = Q.q[r][1] - k[g].y;
+            float c = dy * dy;
+            if (D == 3) {
+                const float dz = Q.q[r][2] - k[g].z;
+                c = __builtin_fmaf(dz, dz, c);
             }
-            const float p = ex2(key_h<D>(k) - c);
+            c = __builtin_fmaf(dx, dx, c);
+            e[g] = rec_h<D>(k[g]) - c;
+        }
+        float tm = fmaxf(fmaxf(fmaxf(e[0], e[1]), fmaxf(e[2], e[3])),
+                         fmaxf(fmaxf(e[4], e[5]), fmaxf(e[6], e[7])));
+        const float mn = fmaxf(Q.sh[r], tm);
+        const float sc = ex2(Q.sh[r] - mn);
+        Q.sh[r] = mn;
+        Q.s[r] *= sc;
+        if (BARY) {
+#pragma unroll
+            for (int t = 0; t < D; ++t) Q.b[r][t] *= sc;
+        }
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const float p = ex2(e[g] - mn);
             Q.s[r] += p;
             if (BARY) {
-                Q.b[r][0] = __builtin_fmaf(p, dx, Q.b[r][0]);
-                Q.b[r][1] = __builtin_fmaf(p, dy, Q.b[r][1]);
-                if (D == 3) Q.b[r][2] = __builtin_fmaf(p, dz, Q.b[r][2]);
+                Q.b[r][0] = __builtin_fmaf(p, Q.q[r][0] - k[g].x, Q.b[r][0]);
+                Q.b[r][1] = __builtin_fmaf(p, Q.q[r][1] - k[g].y, Q.b[r][1]);
+                if (D == 3) Q.b[r][2] = __builtin_fmaf(p, Q.q[r][2] - k[g].z, Q.b[r][2]);
             }
         }
     }
 }
 
-// Safe accumulation over n staged keys (n a multiple of kGroup).
-template <int D, int R, bool BARY>
-__device__ __forceinline__ void accum_safe(const float4* tile, int n, QueryRegs<D, R>& Q) {
-    for (int j0 = 0; j0 < n; j0 += kGroup) {
-        float e[R][kGroup];
-#pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-            const float4 k = tile[j0 + g];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const float dx = Q.q[r][0] - k.x;
-                const float dy = Q.q[r][1] - k.y;
-                float c = dy * dy;
-                if (D == 3) {
-                    const float dz = Q.q[r][2] - k.z;
-                    c = __builtin_fmaf(dz, dz, c);
-                }
-                c = __builtin_fmaf(dx, dx, c);
-                e[r][g] = key_h<D>(k) - c;
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            float tm = e[r][0];
-#pragma unroll
-            for (int g = 1; g < kGroup; ++g) tm = fmaxf(tm, e[r][g]);
-            const float mn = fmaxf(Q.sh[r], tm);
-            const float sc = ex2(Q.sh[r] - mn);
-            Q.sh[r] = mn;
-            Q.s[r] *= sc;
-            if (BARY) {
-#pragma unroll
-                for (int t = 0; t < D; ++t) Q.b[r][t] *= sc;
-            }
-#pragma unroll
-            for (int g = 0; g < kGroup; ++g) {
-                const float p = ex2(e[r][g] - mn);
-                Q.s[r] += p;
-                if (BARY) {
-                    const float4 k = tile[j0 + g];
-                    Q.b[r][0] = __builtin_fmaf(p, Q.q[r][0] - k.x, Q.b[r][0]);
-                    Q.b[r][1] = __builtin_fmaf(p, Q.q[r][1] - k.y, Q.b[r][1]);
-                    if (D == 3) Q.b[r][2] = __builtin_fmaf(p, Q.q[r][2] - k.z, Q.b[r][2]);
-                }
-            }
-        }
-    }
-}
-
-// Sweep keys [k0, k1) of job J for the block's queries, staging tiles in LDS.
+// Accumulate keys [k0, k1) (wave-uniform, multiples of 8; the record array is
+// padded with h = -inf records up to a multiple of 8).
 template <int D, int R, bool LAGGED, bool BARY>
-__device__ __forceinline__ void sweep_range(const Job& J, int k0, int k1, float4* tile,
-                                            QueryRegs<D, R>& Q) {
-    for (int t0 = k0; t0 < k1; t0 += kTile) {
-        const int t1 = min(t0 + kTile, k1);
-        __syncthreads();
-        stage_tile<D>(tile, J.kc, J.kh, t0, t1);
-        __syncthreads();
-        const int cnt = t1 - t0;
-        if (LAGGED) {
-            accum_lagged<D, R, BARY>(tile, (cnt + 3) & ~3, Q);
-        } else {
-            accum_safe<D, R, BARY>(tile, (cnt + kGroup - 1) & ~(kGroup - 1), Q);
+__device__ __forceinline__ void sweep_keys(const float4* __restrict__ rec, int k0, int k1,
+                                           QueryRegs<D, R>& Q) {
+    if (LAGGED) {
+#pragma unroll 2
+        for (int k = k0; k < k1; k += 4) {
+            const float4 a = rec[k], b = rec[k + 1], c = rec[k + 2], d = rec[k + 3];
+            pair_lagged<D, R, BARY>(a, Q);
+            pair_lagged<D, R, BARY>(b, Q);
+            pair_lagged<D, R, BARY>(c, Q);
+            pair_lagged<D, R, BARY>(d, Q);
+        }
+    } else {
+        for (int k = k0; k < k1; k += 8) {
+            float4 kk[8];
+#pragma unroll
+            for (int g = 0; g < 8; ++g) kk[g] = rec[k + g];
+            group_safe<D, R, BARY>(kk, Q);
         }
     }
 }
 
 template <int D, int R>
-__device__ __forceinline__ void init_queries(const Job& J, int qbase, float kappa, bool lagged,
-                                             QueryRegs<D, R>& Q) {
+__device__ __forceinline__ void load_queries(const Job& J, int qbase, int lane, float kappa,
+                                             bool lagged, QueryRegs<D, R>& Q) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int q = qbase + r * kBlock + (int)threadIdx.x;
+        const int q = qbase + r * 64 + lane;
         float4 c = make_float4(0.f, 0.f, 0.f, 0.f);
         float sh = lagged ? 0.f : -FLT_MAX;
         if (q < J.nq) {
-            c = J.qc[q];
+            c = J.qrec[q];
             if (lagged) sh = -J.qpot[q] * kappa;
         }
         Q.q[r][0] = c.x;
@@ -181,6 +168,24 @@ __device__ __forceinline__ void init_queries(const Job& J, int qbase, float kapp
     }
 }
 
+// Combine two partials (m1, s1, b1) += (m2, s2, b2).
+template <int D, bool LAGGED, bool BARY>
+__device__ __forceinline__ void combine(float& m1, float& s1, float* b1, float m2, float s2,
+                                        const float* b2) {
+    if (LAGGED) {
+        s1 += s2;
+        if (BARY)
+            for (int t = 0; t < D; ++t) b1[t] += b2[t];
+    } else {
+        const float mn = fmaxf(m1, m2);
+        const float c1 = ex2(m1 - mn), c2 = ex2(m2 - mn);
+        m1 = mn;
+        s1 = s1 * c1 + s2 * c2;
+        if (BARY)
+            for (int t = 0; t < D; ++t) b1[t] = b1[t] * c1 + b2[t] * c2;
+    }
+}
+
 // Write the final value of one query row given (shift, sum, offset sums).
 template <int D>
 __device__ __forceinline__ void finish_row(const Job& J, int q, float m, float s, const float* b,
@@ -190,9 +195,10 @@ __device__ __forceinline__ void finish_row(const Job& J, int q, float m, float s
     const float old = J.qpot[q];
     const float nv = J.self_avg ? 0.5f * (old + t) : t;
     J.out_pot[q] = nv;
-    if (J.out_h) {
+    if (J.out_rec) {
         const float lw = J.qlog2w ? J.qlog2w[q] : J.qlog2w_s;
-        J.out_h[q] = __builtin_fmaf(nv, kappa, lw);
+        float* hp = reinterpret_cast<float*>(J.out_rec + q) + (D == 2 ? 2 : 3);
+        *hp = __builtin_fmaf(nv, kappa, lw);
     }
     if (J.out_bary) {
         const float inv = -inv_sqrt_kappa / s;
@@ -201,20 +207,20 @@ __device__ __forceinline__ void finish_row(const Job& J, int q, float m, float s
     }
 }
 
-// Recompute the flagged rows of this block with a tracked maximum over every key
-// of the job, the whole block cooperating on one row at a time.
+// Recompute the flagged rows with a tracked maximum over every key of the job,
+// the whole block cooperating on one row at a time.
 template <int D, bool BARY>
-__device__ void rescue_rows(const Job& J, const int* flist, int nflag, int qbase, float kappa,
+__device__ void rescue_rows(const Job& J, const int* flist, int nflag, float kappa,
                             float inv_kappa, float inv_sqrt_kappa) {
     __shared__ float red[kBlock * (2 + D)];
     for (int f = 0; f < nflag; ++f) {
-        const int q = qbase + flist[f];
-        const float4 qc = J.qc[q];
+        const int q = flist[f];
+        const float4 qc = J.qrec[q];
         float m = -FLT_MAX, s = 0.f, b[D];
 #pragma unroll
         for (int t = 0; t < D; ++t) b[t] = 0.f;
         for (int j = (int)threadIdx.x; j < J.nk; j += kBlock) {
-            const float4 k = J.kc[j];
+            const float4 k = J.krec[j];
             const float dx = qc.x - k.x, dy = qc.y - k.y;
             float c = dy * dy;
             float dz = 0.f;
@@ -223,7 +229,7 @@ __device__ void rescue_rows(const Job& J, const int* flist, int nflag, int qbase
                 c = __builtin_fmaf(dz, dz, c);
             }
             c = __builtin_fmaf(dx, dx, c);
-            const float e = J.kh[j] - c;
+            const float e = rec_h<D>(k) - c;
             if (e > m) {
                 const float sc = ex2(m - e);
                 s *= sc;
@@ -263,84 +269,195 @@ __device__ void rescue_rows(const Job& J, const int* flist, int nflag, int qbase
     }
 }
 
-// After the block's key range is done: either finish directly (one split) or
-// publish partials and let the last block to arrive merge all splits.
-template <int D, int R, bool LAGGED, bool BARY>
-__device__ __forceinline__ void publish_and_merge(const Job& J, int qb, int split, int qbase,
-                                                  QueryRegs<D, R>& Q, float kappa,
-                                                  float inv_kappa, float inv_sqrt_kappa) {
-    __shared__ int s_last;
-    __shared__ int s_nflag;
-    __shared__ int s_flist[kBlock * R];
-    const int nqpad = J.nqb * kBlock * R;
-    if (J.splits > 1) {
+// Shared memory of one sweep work unit.
+template <int D, int R>
+struct SweepSmem {
+    float part[kBlock * R * (2 + D)];  // wave-split partials / merge scratch
+    int flist[kBlock * R];             // rows flagged for recomputation
+    int nflag;
+    int last;
+};
+
+// Finish (or flag) the rows held as (m, s, b) by this thread; rows of a lagged
+// sweep whose sum is out of range go to the block's rescue list.
+template <int D, bool LAGGED>
+__device__ __forceinline__ void finish_or_flag(const Job& J, int q, float m, float s, const float* b,
+                                               int* flist, int* nflag, float kappa, float inv_kappa,
+                                               float inv_sqrt_kappa) {
+    if (q >= J.nq) return;
+    if (LAGGED && !(s >= kSumLo && s <= kSumHi)) {
+        const int idx = atomicAdd(nflag, 1);
+        flist[idx] = q;
+        return;
+    }
+    finish_row<D>(J, q, m, s, b, kappa, inv_kappa, inv_sqrt_kappa);
+}
+
+// One work unit: queries of query-block qb, keys of split `split`.
+//   QW = 4 / WS query groups of 64 R queries per block.
+template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP = false>
+__device__ __forceinline__ void sweep_unit(const Job& J, int qb, int split, float kappa,
+                                           float inv_kappa, float inv_sqrt_kappa,
+                                           SweepSmem<D, R>& sm) {
+    constexpr int QW = 4 / WS;
+    constexpr int NC = 2 + D;                  // components of a partial
+    constexpr int QB = QW * 64 * R;            // queries per block
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = (int)threadIdx.x & 63;
+    const int qwave = wave % QW;
+    const int kpart = wave / QW;
+    const int qblock0 = qb * QB;
+    const int qbase = qblock0 + qwave * 64 * R;
+
+    QueryRegs<D, R> Q;
+    load_queries<D, R>(J, qbase, lane, kappa, LAGGED, Q);
+    {
+        const int s0 = split * J.kps;
+        const int kpw = J.kps / WS;
+        const int k0 = min(J.nkpad, s0 + kpart * kpw);
+        const int k1 = min(J.nkpad, k0 + kpw);
+        sweep_keys<D, R, LAGGED, BARY>(J.krec, k0, k1, Q);
+    }
+
+    if (threadIdx.x == 0) sm.nflag = 0;
+    // combine the WS wave partials of each query in LDS (waves with kpart 0 keep the result)
+    if (WS > 1) {
+        __syncthreads();
+        if (kpart > 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int ql = qbase + r * kBlock + (int)threadIdx.x;
-            float* P = J.part + ql;
-            const size_t stride = (size_t)J.splits * nqpad;
-            P[(size_t)split * nqpad] = Q.sh[r];
-            P[stride + (size_t)split * nqpad] = Q.s[r];
-            if (BARY) {
-#pragma unroll
-                for (int t = 0; t < D; ++t) P[(2 + t) * stride + (size_t)split * nqpad] = Q.b[r][t];
+            for (int r = 0; r < R; ++r) {
+                float* P = sm.part + (((kpart - 1) * QW + qwave) * R + r) * 64 * NC + lane;
+                P[0] = Q.sh[r];
+                P[64] = Q.s[r];
+                if (BARY)
+                    for (int t = 0; t < D; ++t) P[(2 + t) * 64] = Q.b[r][t];
             }
         }
+        __syncthreads();
+        if (kpart == 0) {
+            for (int kp = 1; kp < WS; ++kp) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float* P = sm.part + (((kp - 1) * QW + qwave) * R + r) * 64 * NC + lane;
+                    float b2[D];
+                    if (BARY)
+                        for (int t = 0; t < D; ++t) b2[t] = P[(2 + t) * 64];
+                    combine<D, LAGGED, BARY>(Q.sh[r], Q.s[r], Q.b[r], P[0], P[64], b2);
+                }
+            }
+        }
+    } else {
+        __syncthreads();
+    }
+
+    if (J.splits == 1) {
+        if (kpart == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                finish_or_flag<D, LAGGED>(J, qbase + r * 64 + lane, Q.sh[r], Q.s[r], Q.b[r],
+                                          sm.flist, &sm.nflag, kappa, inv_kappa, inv_sqrt_kappa);
+        }
+    } else {
+        // publish this block's partial, then the last block of the query block merges
+        const int nqpad = J.nqb * QB;
+        const size_t cstride = (size_t)J.splits * nqpad;
+        if (kpart == 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float* P = J.part + (size_t)split * nqpad + qbase + r * 64 + lane;
+                if (!LAGGED) P[0] = Q.sh[r];
+                P[cstride] = Q.s[r];
+                if (BARY)
+                    for (int t = 0; t < D; ++t) P[(2 + t) * cstride] = Q.b[r][t];
+            }
+        }
+        // separate-merge mode: a later kernel (k_merge) combines the splits
+        if (SEP) return;
         __threadfence();
         __syncthreads();
         if (threadIdx.x == 0) {
             const unsigned prev = atomicAdd(&J.ticket[qb], 1u);
-            s_last = (prev == (unsigned)(J.splits - 1));
+            sm.last = (prev == (unsigned)(J.splits - 1));
         }
         __syncthreads();
-        if (!s_last) return;
+        if (!sm.last) return;
         __threadfence();
-        // merge every split's partials for this block's queries
+        // all 256 threads merge: TPQ threads per query, splits strided among them
+        constexpr int TPQ = (QB >= kBlock) ? 1 : kBlock / QB;
+        constexpr int QPT = (QB >= kBlock) ? QB / kBlock : 1;
+        const int sub = (int)threadIdx.x / (kBlock / TPQ * 1) % TPQ;
+        const int slot = (int)threadIdx.x % (kBlock / TPQ);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int ql = qbase + r * kBlock + (int)threadIdx.x;
-            const float* P = J.part + ql;
-            const size_t stride = (size_t)J.splits * nqpad;
-            float M = -FLT_MAX;
-            for (int sp = 0; sp < J.splits; ++sp) M = fmaxf(M, P[(size_t)sp * nqpad]);
-            float S = 0.f, B[D];
-#pragma unroll
-            for (int t = 0; t < D; ++t) B[t] = 0.f;
-            for (int sp = 0; sp < J.splits; ++sp) {
-                const float sc = LAGGED ? 1.f : ex2(P[(size_t)sp * nqpad] - M);
-                S = __builtin_fmaf(P[stride + (size_t)sp * nqpad], sc, S);
-                if (BARY) {
-#pragma unroll
-                    for (int t = 0; t < D; ++t)
-                        B[t] = __builtin_fmaf(P[(2 + t) * stride + (size_t)sp * nqpad], sc, B[t]);
+        for (int u = 0; u < QPT; ++u) {
+            const int ql = slot + u * (kBlock / TPQ);   // query index within the block
+            const int q = qblock0 + ql;
+            float m, s, b[D];
+            if (LAGGED) m = (q < J.nq) ? -J.qpot[q] * kappa : 0.f;
+            else m = -FLT_MAX;
+            s = 0.f;
+            for (int t = 0; t < D; ++t) b[t] = 0.f;
+            for (int sp = sub; sp < J.splits; sp += TPQ) {
+                const float* P = J.part + (size_t)sp * nqpad + q;
+                float b2[D];
+                if (BARY)
+                    for (int t = 0; t < D; ++t) b2[t] = P[(2 + t) * cstride];
+                combine<D, LAGGED, BARY>(m, s, b, LAGGED ? m : P[0], P[cstride], b2);
+            }
+            if (TPQ > 1) {
+                float* S = sm.part + ((sub * (kBlock / TPQ) + slot) * NC);
+                S[0] = m;
+                S[1] = s;
+                if (BARY)
+                    for (int t = 0; t < D; ++t) S[2 + t] = b[t];
+                __syncthreads();
+                if (sub == 0) {
+                    for (int k2 = 1; k2 < TPQ; ++k2) {
+                        const float* S2 = sm.part + ((k2 * (kBlock / TPQ) + slot) * NC);
+                        float b2[D];
+                        if (BARY)
+                            for (int t = 0; t < D; ++t) b2[t] = S2[2 + t];
+                        combine<D, LAGGED, BARY>(m, s, b, S2[0], S2[1], b2);
+                    }
                 }
             }
-            Q.sh[r] = M;
-            Q.s[r] = S;
-#pragma unroll
-            for (int t = 0; t < D; ++t) Q.b[r][t] = B[t];
+            if (sub == 0)
+                finish_or_flag<D, LAGGED>(J, q, m, s, b, sm.flist, &sm.nflag, kappa, inv_kappa,
+                                          inv_sqrt_kappa);
         }
         if (threadIdx.x == 0) J.ticket[qb] = 0u;
     }
     if (LAGGED) {
-        if (threadIdx.x == 0) s_nflag = 0;
         __syncthreads();
+        const int nflag = sm.nflag;
+        if (nflag > 0) rescue_rows<D, BARY>(J, sm.flist, nflag, kappa, inv_kappa, inv_sqrt_kappa);
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int q = qbase + r * kBlock + (int)threadIdx.x;
-        if (q >= J.nq) continue;
-        if (LAGGED && !(Q.s[r] >= kSumLo && Q.s[r] <= kSumHi)) {
-            const int idx = atomicAdd(&s_nflag, 1);
-            s_flist[idx] = r * kBlock + (int)threadIdx.x;
-            continue;
+}
+
+// Separate merge: one thread per query row combines the partials of every split
+// (fixed order), then finishes or flags the row; flagged rows are recomputed by
+// the block.  Used when many small blocks make per-block merging expensive.
+template <int D, bool LAGGED, bool BARY>
+__device__ __forceinline__ void merge_rows(const Job& J, int q, int nqpad, float kappa,
+                                           float inv_kappa, float inv_sqrt_kappa, int* flist,
+                                           int* nflag) {
+    const size_t cstride = (size_t)J.splits * nqpad;
+    if (q < J.nq) {
+        float m = LAGGED ? -J.qpot[q] * kappa : -FLT_MAX;
+        float s = 0.f, b[D];
+        for (int t = 0; t < D; ++t) b[t] = 0.f;
+        for (int sp = 0; sp < J.splits; ++sp) {
+            const float* P = J.part + (size_t)sp * nqpad + q;
+            float b2[D];
+            if (BARY)
+                for (int t = 0; t < D; ++t) b2[t] = P[(2 + t) * cstride];
+            combine<D, LAGGED, BARY>(m, s, b, LAGGED ? m : P[0], P[cstride], b2);
         }
-        finish_row<D>(J, q, Q.sh[r], Q.s[r], Q.b[r], kappa, inv_kappa, inv_sqrt_kappa);
+        finish_or_flag<D, LAGGED>(J, q, m, s, b, flist, nflag, kappa, inv_kappa, inv_sqrt_kappa);
     }
     if (LAGGED) {
         __syncthreads();
-        const int nflag = s_nflag;
-        if (nflag > 0) rescue_rows<D, BARY>(J, s_flist, nflag, qbase, kappa, inv_kappa, inv_sqrt_kappa);
+        const int n = *nflag;
+        if (n > 0) rescue_rows<D, BARY>(J, flist, n, kappa, inv_kappa, inv_sqrt_kappa);
     }
 }
 

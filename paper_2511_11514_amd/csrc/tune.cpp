@@ -11,7 +11,7 @@ namespace ct {
 
 namespace {
 struct Entry {
-    int R, bpc, us;
+    int R, WS, bpc, sep, us;
 };
 std::mutex g_mu;
 std::map<std::tuple<int, int, int>, Entry> g_table;
@@ -27,18 +27,22 @@ Schedule schedule_for(int d, int64_t nq, int64_t nk) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_table.find({d, size_class(nq), size_class(nk)});
-        if (it != g_table.end()) return Schedule{it->second.R, it->second.bpc};
+        if (it != g_table.end())
+            return Schedule{it->second.R, it->second.WS, it->second.bpc, it->second.sep};
     }
-    // untuned default: more queries per lane when there are many queries
-    Schedule s{4, 8};
-    if (nq < 32768) s.R = 2;
-    if (nq < 8192) s.R = 1;
+    // untuned default: more queries per lane and fewer key-splitting waves when
+    // there are many queries
+    Schedule s{2, 4, 16, 1};
+    if (nq < 65536) s = Schedule{2, 2, 4, 1};
+    if (nq < 8192) s = Schedule{4, 4, 2, 1};
+    (void)d;
+    (void)nk;
     return s;
 }
 
-void tuning_record(int d, int64_t nq, int64_t nk, int R, int bpc, int us) {
+void tuning_record(int d, int64_t nq, int64_t nk, const Schedule& sc, int us) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_table[{d, size_class(nq), size_class(nk)}] = Entry{R, bpc, us};
+    g_table[{d, size_class(nq), size_class(nk)}] = Entry{sc.R, sc.WS, sc.blocks_per_cu, sc.sep, us};
 }
 
 }  // namespace ct
@@ -50,18 +54,19 @@ extern "C" int32_t ct_tuning_count(void) {
     return (int32_t)g_table.size();
 }
 
-extern "C" ct_status ct_tuning_entry(int32_t i, int32_t* out6) {
-    if (!out6) return fail(CT_E_ARG, "out6 is null");
+extern "C" ct_status ct_tuning_entry(int32_t i, int32_t* out7) {
+    if (!out7) return fail(CT_E_ARG, "out7 is null");
     std::lock_guard<std::mutex> lk(g_mu);
     if (i < 0 || i >= (int32_t)g_table.size()) return fail(CT_E_ARG, "entry %d out of range", i);
     auto it = g_table.begin();
     std::advance(it, i);
-    out6[0] = std::get<0>(it->first);
-    out6[1] = std::get<1>(it->first);
-    out6[2] = std::get<2>(it->first);
-    out6[3] = it->second.R;
-    out6[4] = it->second.bpc;
-    out6[5] = it->second.us;
+    out7[0] = std::get<0>(it->first);
+    out7[1] = std::get<1>(it->first);
+    out7[2] = std::get<2>(it->first);
+    out7[3] = it->second.R;
+    out7[4] = it->second.WS;
+    out7[5] = it->second.bpc * 10 + it->second.sep;
+    out7[6] = it->second.us;
     return CT_OK;
 }
 
@@ -70,10 +75,11 @@ extern "C" ct_status ct_tuning_save(const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return fail(CT_E_ARG, "cannot open %s for writing", path);
     std::lock_guard<std::mutex> lk(g_mu);
-    std::fprintf(f, "# d qclass kclass R blocks_per_cu us\n");
+    std::fprintf(f, "# d qclass kclass R WS blocks_per_cu separate_merge us\n");
     for (auto& kv : g_table)
-        std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                     std::get<2>(kv.first), kv.second.R, kv.second.bpc, kv.second.us);
+        std::fprintf(f, "%d %d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                     std::get<2>(kv.first), kv.second.R, kv.second.WS, kv.second.bpc,
+                     kv.second.sep, kv.second.us);
     std::fclose(f);
     return CT_OK;
 }
@@ -86,13 +92,15 @@ extern "C" ct_status ct_tuning_load(const char* path) {
     std::lock_guard<std::mutex> lk(g_mu);
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
-        int d, qc, kc, R, b, us;
-        if (std::sscanf(line, "%d %d %d %d %d %d", &d, &qc, &kc, &R, &b, &us) != 6) continue;
-        if ((d != 2 && d != 3) || (R != 1 && R != 2 && R != 4 && R != 8) || b < 1 || b > 16) {
+        int d, qc, kc, R, ws, b, sep, us;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &d, &qc, &kc, &R, &ws, &b, &sep, &us) != 8)
+            continue;
+        if ((d != 2 && d != 3) || (R != 1 && R != 2 && R != 4 && R != 8) ||
+            (ws != 1 && ws != 2 && ws != 4) || b < 1 || b > 16 || (sep != 0 && sep != 1)) {
             std::fclose(f);
             return fail(CT_E_ARG, "bad tuning entry: %s", line);
         }
-        g_table[{d, qc, kc}] = Entry{R, b, us};
+        g_table[{d, qc, kc}] = Entry{R, ws, b, sep, us};
     }
     std::fclose(f);
     return CT_OK;

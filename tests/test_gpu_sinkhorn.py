@@ -130,3 +130,29 @@ def test_tiny_and_identical(ct):
     g = _run(ct, x, y, None, 0.05, 30)
     r = _oracle(x, y, None, 0.05, 30)
     _compare(g, r, 5, 3, None)
+
+
+def _size_class(n):
+    c = 0
+    while (1 << c) < n:
+        c += 1
+    return c
+
+
+@pytest.mark.parametrize("R,WS,bpc,sep", [(1, 1, 2, 0), (2, 4, 8, 0), (4, 2, 16, 0), (8, 1, 1, 0),
+                                          (1, 4, 16, 1), (2, 2, 4, 1), (4, 1, 8, 1), (8, 4, 2, 1)])
+def test_every_schedule_matches_oracle(ct, tmp_path, R, WS, bpc, sep):
+    """Each tile/split/merge schedule the tuner may pick gives the same result."""
+    d, T, M, eps, iters = 2, 1500, 2100, 0.01, 15
+    x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=T, M=M)
+    f = tmp_path / "tune.txt"
+    cT, cM = _size_class(T), _size_class(M)
+    f.write_text(f"{d} {cT} {cM} {R} {WS} {bpc} {sep} 0\n{d} {cM} {cT} {R} {WS} {bpc} {sep} 0\n")
+    ct.tuning_clear()
+    ct.tuning_load(str(f))
+    try:
+        g = _run(ct, x, y, w, eps, iters)
+    finally:
+        ct.tuning_clear()
+    r = _oracle(x, y, w, eps, iters)
+    _compare(g, r, T, M, w)
