@@ -11,7 +11,8 @@ grad_{s_j} k(s_j, s_i) = (2/h)(s_i - s_j) k(s_j, s_i), this is
 Readings where the paper is silent:
 * bandwidth by the median heuristic of the SVGD paper the method cites:
   h = med^2 / ln n, med = median of the n(n-1)/2 distances |x_i - x_j|, i < j
-  (mean of the two middle values when that count is even); h = 1 when n = 1;
+  (mean of the two middle values when that count is even); h = 1 when n = 1 or
+  when the median distance is zero (all samples coincide);
 * the reference q is a Gaussian mixture with diagonal covariances, optionally
   mixed with a uniform density of mass rho on [0,1]^d:
     q(x) = (1 - rho) sum_k pi_k N(x; mu_k, diag sigma_k^2) + rho 1[x in [0,1]^d];
@@ -72,6 +73,8 @@ def median_bandwidth(x) -> float:
     npair = dist.shape[0]
     srt = np.partition(dist, [(npair - 1) // 2, npair // 2])
     med = 0.5 * (srt[(npair - 1) // 2] + srt[npair // 2])
+    if med == 0.0:
+        return 1.0
     return float(med * med / np.log(n))
 
 

@@ -1,0 +1,71 @@
+"""GPU planner (ct_plan, Sec. II-C) against the oracle's outer loop.  Parity is
+checked per outer step from identical controls (the end state of a multi-step
+run is not unique, Sec. III-C), plus monotone decrease of S over the planner
+workload's ten steps."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _c1():
+    cfg = W.CONFIGS["planner_2d"]
+    e = cfg.extra
+    x, y, w, g = W.config_inputs(cfg)
+    rng = np.random.default_rng(cfg.seed + 1)
+    u0 = rng.normal(size=(cfg.T, 2)) * e["u_std"]
+    return cfg, e, y, w, g, u0
+
+
+def test_sinkhorn_plan_one_step_parity(ct):
+    cfg, e, y, w, g, u0 = _c1()
+    dev = torch.device("cuda")
+    s0 = np.array(e["s0"])
+    Q, R = np.eye(2), 0.01 * np.eye(2)
+    u1, s, hist = ct.plan("double_integrator", s0, u0, e["dt"], Q, R, "sinkhorn", 1, 0.5,
+                          y=torch.as_tensor(y, device=dev), w=torch.as_tensor(w, device=dev),
+                          eps=cfg.eps, iters=cfg.iters)
+    r_u1, r_s, r_obj, r_a, r_v = oracle.plan_step("double_integrator", s0, u0, e["dt"], Q, R,
+                                                 "sinkhorn", step=0.5, y=y, w=w, eps=cfg.eps,
+                                                 iters=cfg.iters)
+    assert abs(hist[0] - r_obj) / abs(r_obj) < 1e-5
+    assert rel(u1 - u0, r_u1 - u0) < 1e-5
+    np.testing.assert_allclose(s, oracle.rollout("double_integrator", s0, u1, e["dt"]), rtol=1e-12)
+
+
+def test_sinkhorn_plan_ten_steps_decrease(ct):
+    cfg, e, y, w, g, u0 = _c1()
+    dev = torch.device("cuda")
+    s0 = np.array(e["s0"])
+    Q, R = np.eye(2), 0.01 * np.eye(2)
+    _u, _s, hist = ct.plan("double_integrator", s0, u0, e["dt"], Q, R, "sinkhorn", e["outer"], 0.5,
+                           y=torch.as_tensor(y, device=dev), w=torch.as_tensor(w, device=dev),
+                           eps=cfg.eps, iters=cfg.iters)
+    _ru, _rs, rhist = oracle.plan("double_integrator", s0, u0, e["dt"], Q, R, "sinkhorn",
+                                  e["outer"], step=0.5, y=y, w=w, eps=cfg.eps, iters=cfg.iters)
+    assert np.all(np.diff(hist) < 0), hist
+    assert hist[-1] < 0.05 * hist[0]
+    np.testing.assert_allclose(hist, rhist, rtol=1e-3)
+
+
+def test_svgd_unicycle_plan_one_step_parity(ct):
+    cfg = W.CONFIGS["roofline_2d"]
+    e = cfg.extra
+    T = 700
+    _x, _y, _w, g = W.config_inputs(cfg, T=T, M=16)
+    rng = np.random.default_rng(cfg.seed + 1)
+    u0 = np.stack([np.full(T, e["v0"]), rng.normal(size=T) * e["omega_std"]], axis=1)
+    s0 = np.array(e["s0"])
+    Q, R = np.eye(2), 0.01 * np.eye(2)
+    dev = torch.device("cuda")
+    u1, _s, hist = ct.plan("unicycle", s0, u0, e["dt"], Q, R, "svgd", 1, 0.5,
+                           gmm=ct.GMM.from_numpy(g, dev))
+    r_u1, _rs, r_obj, _ra, _rv = oracle.plan_step("unicycle", s0, u0, e["dt"], Q, R, "svgd",
+                                                 step=0.5, gmm=g)
+    assert abs(hist[0] - r_obj) / abs(r_obj) < 1e-5
+    assert rel(u1 - u0, r_u1 - u0) < 1e-5

@@ -1,0 +1,69 @@
+"""GPU parity of ct_svgd_grad against the FP64 oracle (Sec. II-B, eq. 4): the
+mixture score, the exact median bandwidth and the Stein flow phi.
+Tolerance 1e-5 norm-wise relative error (float32 path vs float64 oracle)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _gpu(ct, x, g, h=None):
+    dev = torch.device("cuda")
+    phi, hu, sc = ct.svgd_grad(torch.as_tensor(x, device=dev), ct.GMM.from_numpy(g, dev), h,
+                               return_score=True)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy(), float(hu.item()), sc.cpu().numpy()
+
+
+def _oracle(x, g, h=None):
+    sc = oracle.gmm_score(x, g.weights, g.means, g.sigmas, g.floor)
+    hh = oracle.median_bandwidth(x) if h is None else h
+    return oracle.svgd_phi(x, sc, hh), hh, sc
+
+
+@pytest.mark.parametrize("cfg,T", [("grad_2d", 1000), ("grad_2d", 4096), ("autograd_3d", 777),
+                                   ("roofline_2d", 1531)])
+def test_parity(ct, cfg, T):
+    x, _y, _w, g = W.config_inputs(W.CONFIGS[cfg], T=T, M=16)
+    phi, h, sc = _gpu(ct, x, g)
+    rphi, rh, rsc = _oracle(x, g)
+    e = dict(score=rel(sc, rsc), h=abs(h - rh) / rh, phi=rel(phi, rphi))
+    print(cfg, T, " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    assert e["score"] < TOL and e["h"] < 1e-6 and e["phi"] < TOL, e
+
+
+def test_fixed_bandwidth_and_odd_even_pair_counts(ct):
+    x, _y, _w, g = W.config_inputs(W.CONFIGS["grad_2d"], T=301, M=16)
+    phi, h, _ = _gpu(ct, x, g, h=0.0123)
+    rphi, _, _ = _oracle(x, g, h=0.0123)
+    assert h == pytest.approx(0.0123, rel=1e-7)
+    assert rel(phi, rphi) < TOL
+    for T in (2, 3, 4, 5, 64, 65):        # pair counts 1, 3, 6, 10, 2016, 2080
+        xs = x[:T]
+        _p, hg, _s = _gpu(ct, xs, g)
+        assert abs(hg - oracle.median_bandwidth(xs)) <= 1e-6 * oracle.median_bandwidth(xs)
+
+
+def test_degenerate_cases(ct):
+    g = W.gmm_params(np.random.default_rng(0), 1, 2, 0.05, 0.1)
+    x1 = np.array([[0.3, 0.6]], np.float32)
+    phi, h, sc = _gpu(ct, x1, g)
+    assert h == 1.0
+    np.testing.assert_allclose(phi, sc, rtol=1e-6)          # one sample: phi = score
+    mu, sg = g.means[0].astype(np.float64), g.sigmas[0].astype(np.float64)
+    np.testing.assert_allclose(sc[0], -(x1[0] - mu) / sg ** 2, rtol=1e-6)
+    x2 = np.array([[0.3, 0.6], [0.35, 0.58]], np.float32)
+    phi, h, sc = _gpu(ct, x2, g)
+    rphi, rh, _ = _oracle(x2, g)
+    assert abs(h - rh) / rh < 1e-6 and rel(phi, rphi) < TOL
+    xc = np.repeat(x1, 7, axis=0)                            # coincident samples: h = 1
+    phi, h, sc = _gpu(ct, xc, g)
+    assert h == 1.0
+    np.testing.assert_allclose(phi, sc, rtol=1e-6)
