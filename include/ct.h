@@ -135,12 +135,20 @@ ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const floa
  *                             (every problem needs T_b >= 1, M_b >= 1)
  *   x, y, w, grad_x, grad_w   concatenations in that order (w may be NULL)
  *   value         device [B] or NULL (requires CT_VALUE)
- * CT_WARM_START and CT_REF_CACHED are not supported here (CT_E_ARG).
- * The work list is rebuilt on the host each call and copied into `ws` on
- * `stream`; the copy is synchronous with respect to the host (pageable source).
+ * Flags: CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_SAFE_LSE (others: CT_E_ARG).
+ * The workspace must first be prepared for this batch (same B, offsets, d, iters,
+ * flags) by ct_sinkhorn_batched_prepare, which builds the work list on the host
+ * and copies it into `ws`; ct_sinkhorn_grad_batched itself only enqueues kernels
+ * (no copies, no host synchronisation), so it may be captured into a graph and
+ * replayed as long as the workspace stays prepared.  Returns CT_E_ARG for a
+ * workspace not prepared for this batch.  A value of NaN signals that the
+ * persistent kernel's bounded wait expired (an internal error, never expected).
  */
 size_t ct_sinkhorn_batched_workspace_size(int32_t B, const int64_t* T_off, const int64_t* M_off,
                                           const ct_sinkhorn_opts* o);
+ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* T_off, const int64_t* M_off,
+                                      const ct_sinkhorn_opts* o, void* ws, size_t ws_bytes,
+                                      void* stream);
 ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* T_off, const int64_t* M_off,
                                    const float* x, const float* y, const float* w,
                                    const ct_sinkhorn_opts* o, float* grad_x, float* grad_w,

@@ -70,6 +70,8 @@ _SIGS = {
     "ct_sinkhorn_grad": (c_int32, [P, c_int64, P, P, c_int64, POINTER(SinkhornOpts), P, P, P, P, P,
                                    P, P, c_size_t, P]),
     "ct_sinkhorn_batched_workspace_size": (c_size_t, [c_int32, PI64, PI64, POINTER(SinkhornOpts)]),
+    "ct_sinkhorn_batched_prepare": (c_int32, [c_int32, PI64, PI64, POINTER(SinkhornOpts), P,
+                                              c_size_t, P]),
     "ct_sinkhorn_grad_batched": (c_int32, [c_int32, PI64, PI64, P, P, P, POINTER(SinkhornOpts), P,
                                            P, P, P, c_size_t, P]),
     "ct_svgd_workspace_size": (c_size_t, [c_int64, c_int32]),

@@ -168,12 +168,69 @@ def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor]
     val = torch.empty(B, dtype=torch.float32, device=dev) if value else None
     nbytes = lib().ct_sinkhorn_batched_workspace_size(B, to, mo, ctypes.byref(o))
     wsb = _workspace(nbytes, dev)
+    check("ct_sinkhorn_batched_prepare",
+          lib().ct_sinkhorn_batched_prepare(B, to, mo, ctypes.byref(o), _p(wsb), nbytes, _stream(dev)))
     st = lib().ct_sinkhorn_grad_batched(B, to, mo, _p(x), _p(y), _p(w), ctypes.byref(o), _p(gx),
                                         _p(gw), _p(val), _p(wsb), nbytes, _stream(dev))
     check("ct_sinkhorn_grad_batched", st)
     gxs = [gx[T_off[b]:T_off[b + 1]] for b in range(B)]
     gws = None if gw is None else [gw[M_off[b]:M_off[b + 1]] for b in range(B)]
     return BatchedOut(gxs, gws, val)
+
+
+class BatchedSinkhorn:
+    """A prepared batch: fixed sizes, inputs copied into static buffers, outputs
+    and workspace allocated once.  run() enqueues only kernels (no host sync), so
+    it can be captured into a graph (capture()) and replayed."""
+
+    def __init__(self, xs, ys, ws=None, *, eps: float, iters: int, debias: bool = True,
+                 value: bool = False, grad_w: bool = False, safe: bool = False):
+        B = len(xs)
+        if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
+            raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
+        self.dev = xs[0].device
+        self.d = xs[0].shape[1]
+        self.B = B
+        self.T_off = np.zeros(B + 1, dtype=np.int64)
+        self.M_off = np.zeros(B + 1, dtype=np.int64)
+        for b in range(B):
+            self.T_off[b + 1] = self.T_off[b] + xs[b].shape[0]
+            self.M_off[b + 1] = self.M_off[b] + ys[b].shape[0]
+        self.x = _req(torch.cat([_req(t, "x", self.dev) for t in xs]), "x")
+        self.y = _req(torch.cat([_req(t, "y", self.dev) for t in ys]), "y")
+        self.w = None if ws is None else _req(torch.cat([_req(t, "w", self.dev) for t in ws]), "w")
+        flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
+            (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0)
+        self.o = _opts(self.d, eps, iters, flags)
+        self._to = self.T_off.ctypes.data_as(L.PI64)
+        self._mo = self.M_off.ctypes.data_as(L.PI64)
+        self.grad_x = torch.empty_like(self.x)
+        self.grad_w = torch.empty(int(self.M_off[-1]), dtype=torch.float32,
+                                  device=self.dev) if grad_w else None
+        self.value = torch.empty(B, dtype=torch.float32, device=self.dev) if value else None
+        self.nbytes = lib().ct_sinkhorn_batched_workspace_size(B, self._to, self._mo,
+                                                               ctypes.byref(self.o))
+        self.ws = _workspace(self.nbytes, self.dev)
+        check("ct_sinkhorn_batched_prepare",
+              lib().ct_sinkhorn_batched_prepare(B, self._to, self._mo, ctypes.byref(self.o),
+                                                _p(self.ws), self.nbytes, _stream(self.dev)))
+
+    def run(self) -> None:
+        st = lib().ct_sinkhorn_grad_batched(self.B, self._to, self._mo, _p(self.x), _p(self.y),
+                                            _p(self.w), ctypes.byref(self.o), _p(self.grad_x),
+                                            _p(self.grad_w), _p(self.value), _p(self.ws),
+                                            self.nbytes, _stream(self.dev))
+        check("ct_sinkhorn_grad_batched", st)
+
+    def capture(self):
+        """Capture run() into a torch CUDA (HIP) graph; replay with g.replay()."""
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        return g
+
+    def split(self, t: torch.Tensor, off: np.ndarray):
+        return [t[off[b]:off[b + 1]] for b in range(self.B)]
 
 
 @dataclass

@@ -109,5 +109,7 @@ void profile_end(void* tok, hipStream_t s, int lagged, int bary, int code, int b
 // Tuning table lookup (falls back to a size heuristic).
 Schedule schedule_for(int d, int64_t nq, int64_t nk);
 void tuning_record(int d, int64_t nq, int64_t nk, const Schedule& s, int us);
+// Exact lookup by size classes (no fallback).
+bool tuning_lookup(int d, int qclass, int kclass, Schedule& out);
 
 }  // namespace ct

@@ -40,6 +40,14 @@ Schedule schedule_for(int d, int64_t nq, int64_t nk) {
     return s;
 }
 
+bool tuning_lookup(int d, int qclass, int kclass, Schedule& out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find({d, qclass, kclass});
+    if (it == g_table.end()) return false;
+    out = Schedule{it->second.R, it->second.WS, it->second.bpc, it->second.sep};
+    return true;
+}
+
 void tuning_record(int d, int64_t nq, int64_t nk, const Schedule& sc, int us) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_table[{d, size_class(nq), size_class(nk)}] = Entry{sc.R, sc.WS, sc.blocks_per_cu, sc.sep, us};

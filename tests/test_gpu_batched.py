@@ -1,0 +1,109 @@
+"""Batched persistent path (ct_sinkhorn_grad_batched) against the FP64 oracle
+per problem and against the per-problem path; graph capture and replay."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _ragged(seed, B, tmax, mmax, d=2):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for b in range(B):
+        T = int(rng.integers(1, tmax + 1)) if b % 3 else int(rng.integers(1, 4))
+        M = int(rng.integers(1, mmax + 1))
+        g = W.gmm_params(rng, int(rng.integers(2, 7)), d, 0.03, 0.12)
+        probs.append((W.random_walk(rng, T, d), W.gmm_sample(rng, g, M), W.positive_weights(rng, M)))
+    return probs
+
+
+def _batch(ct, probs, eps, iters, **kw):
+    dev = torch.device("cuda")
+    t = lambda a: torch.as_tensor(a, device=dev)
+    bs = ct.BatchedSinkhorn([t(p[0]) for p in probs], [t(p[1]) for p in probs],
+                            [t(p[2]) for p in probs], eps=eps, iters=iters, value=True,
+                            grad_w=True, **kw)
+    return bs
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_ragged_batch_matches_oracle(ct, d):
+    probs = _ragged(11 + d, 9, 700, 1500, d)
+    eps, iters = 0.01, 25
+    bs = _batch(ct, probs, eps, iters)
+    bs.run()
+    torch.cuda.synchronize()
+    gx = bs.split(bs.grad_x.cpu().numpy(), bs.T_off)
+    gw = bs.split(bs.grad_w.cpu().numpy(), bs.M_off)
+    val = bs.value.cpu().numpy()
+    assert np.isfinite(val).all()
+    for b, (x, y, w) in enumerate(probs):
+        r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
+        e = (rel(gx[b], r.grad_x), rel(gw[b], r.grad_w), abs(val[b] - r.value) / abs(r.value))
+        assert max(e) < TOL, (b, len(x), len(y), e)
+
+
+def test_batched_equals_plain_and_graph_replay(ct):
+    probs = _ragged(21, 12, 900, 2000)
+    eps, iters = 0.01, 30
+    dev = torch.device("cuda")
+    bs = _batch(ct, probs, eps, iters)
+    bs.run()
+    torch.cuda.synchronize()
+    ref_x = bs.grad_x.clone()
+    ref_w = bs.grad_w.clone()
+    ref_v = bs.value.clone()
+    for b, (x, y, w) in enumerate(probs):
+        out = ct.sinkhorn_grad(torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev),
+                               torch.as_tensor(w, device=dev), eps=eps, iters=iters, value=True,
+                               grad_w=True)
+        gx = ref_x[bs.T_off[b]:bs.T_off[b + 1]]
+        assert rel(gx.cpu().numpy(), out.grad_x.cpu().numpy()) < 2e-6
+        assert abs(ref_v[b].item() - out.value.item()) <= 2e-6 * abs(out.value.item())
+    # graph capture and replays, with eager work in between: each replay equals eager
+    g = bs.capture()
+    for rep in range(3):
+        bs.grad_x.zero_()
+        bs.value.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bs.grad_x, ref_x), rep
+        assert torch.equal(bs.grad_w, ref_w), rep
+        assert torch.equal(bs.value, ref_v), rep
+        _ = (torch.randn(1000, device=dev) ** 2).sum().item()
+
+
+def test_unprepared_workspace_is_rejected(ct):
+    import ctypes
+    from paper_2511_11514_amd import _lib
+    probs = _ragged(31, 3, 50, 80)
+    bs = _batch(ct, probs, 0.05, 5)
+    other = torch.empty_like(bs.ws)
+    st = _lib.lib().ct_sinkhorn_grad_batched(bs.B, bs._to, bs._mo, ctypes.c_void_p(bs.x.data_ptr()),
+                                             ctypes.c_void_p(bs.y.data_ptr()), None,
+                                             ctypes.byref(bs.o),
+                                             ctypes.c_void_p(bs.grad_x.data_ptr()), None, None,
+                                             ctypes.c_void_p(other.data_ptr()), bs.nbytes, None)
+    assert st == _lib.CT_E_ARG
+
+
+def test_scaled_batch_workload_sampled(ct):
+    """The 256-problem batch shape at 1/8 of its sizes; four problems checked."""
+    cfg = W.CONFIGS["batched_2d"]
+    probs = W.batch_inputs(cfg, B=48, scale=0.125)
+    bs = _batch(ct, probs, cfg.eps, 40)
+    bs.run()
+    torch.cuda.synchronize()
+    gx = bs.split(bs.grad_x.cpu().numpy(), bs.T_off)
+    val = bs.value.cpu().numpy()
+    for b in (0, 7, 23, 47):
+        x, y, w = probs[b]
+        r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=40)
+        assert rel(gx[b], r.grad_x) < TOL and abs(val[b] - r.value) < TOL * abs(r.value)
