@@ -73,8 +73,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=4)
+    ap.add_argument("--cpu-iters", type=int, default=40,
+                    help="Sinkhorn iterations of the CPU oracle sample")
     ap.add_argument("--no-svgd", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--autotune", action="store_true",
+                    help="re-tune the sweep schedules instead of loading the stored tuning table")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 256 MiB buffer (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -89,6 +95,13 @@ def main() -> int:
     from paper_2511_11514_amd import _lib
 
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = W.CONFIGS["grad_2d"]
     T, M, d, eps, K = cfg.T, cfg.M, cfg.d, cfg.eps, cfg.iters
     x_np, y_np, w_np, g_np = W.config_inputs(cfg)
@@ -108,8 +121,15 @@ def main() -> int:
             out.append(ct.svgd_grad(x, gmm)[0])
         return out
 
-    # pick the sweep schedules for this shape (outside the timed region)
-    ct.autotune_sinkhorn(T, M, d, eps)
+    # sweep schedules for this shape: the stored table written by the autotuner on
+    # an MI355X, or a fresh tuning run (outside the timed region)
+    table = os.path.join(ROOT, "paper_2511_11514_amd", "tuning", "mi355x.txt")
+    if args.autotune or not os.path.exists(table):
+        ct.autotune_sinkhorn(T, M, d, eps)
+        tuned = "autotuned in this run"
+    else:
+        ct.tuning_load(table)
+        tuned = "stored table " + os.path.relpath(table, ROOT)
     try:
         step()
     except ct.CtError as e:
@@ -186,6 +206,7 @@ def main() -> int:
             "sinkhorn_pairs": sk_pairs,
             "svgd_pairs": svgd_pairs,
             "tm_pair_evals_per_s": K * T * M / (ms * 1e-3),
+            "schedules": tuned,
         },
         "roofline": {
             "bound": "alu",
@@ -201,10 +222,56 @@ def main() -> int:
             "ops_per_pair": OPS_PER_PAIR[d],
         },
     }
+    if not args.no_batched:
+        res["batched"] = batched_leg(ct, torch, dev)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(x_np, y_np, w_np, g_np, eps, args.cpu_iters)
     print(json.dumps(res))
     return 0
+
+
+def batched_leg(ct, torch, dev) -> dict:
+    """The 256-problem ragged batch: one persistent launch vs 256 plain calls."""
+    import numpy as np
+    import workloads as W
+    cfg = W.CONFIGS["batched_2d"]
+    probs = W.batch_inputs(cfg)
+    eps, K = cfg.eps, cfg.iters
+    xs = [torch.as_tensor(p[0], device=dev) for p in probs]
+    ys = [torch.as_tensor(p[1], device=dev) for p in probs]
+    bs = ct.BatchedSinkhorn(xs, ys, None, eps=eps, iters=K)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    bs.run()
+    torch.cuda.synchronize()
+    e0.record()
+    bs.run()
+    e1.record()
+    torch.cuda.synchronize()
+    t_b = e0.elapsed_time(e1)
+    plain = [None] * len(probs)
+
+    def run_plain():
+        for b in range(len(probs)):
+            plain[b] = ct.sinkhorn_grad(xs[b], ys[b], None, eps=eps, iters=K).grad_x
+
+    run_plain()
+    torch.cuda.synchronize()
+    e0.record()
+    run_plain()
+    e1.record()
+    torch.cuda.synchronize()
+    t_p = e0.elapsed_time(e1)
+    gx = bs.split(bs.grad_x, bs.T_off)
+    err = max(float((gx[b] - plain[b]).norm() / plain[b].norm()) for b in range(len(probs)))
+    pairs = sum(K * (2.0 * len(p[0]) * len(p[1]) + len(p[0]) ** 2) + len(p[0]) * len(p[1]) +
+                len(p[0]) ** 2 for p in probs)
+    return {"workload": f"batched_2d: {len(probs)} problems, T in {cfg.extra['T_range']}, "
+                        f"M in {cfg.extra['M_range']}, eps={eps}, K={K}, debiased grad_x",
+            "pairs": pairs, "batched_ms": t_b, "plain_ms": t_p, "speedup": t_p / t_b,
+            "batched_pair_evals_per_s": pairs / (t_b * 1e-3),
+            "plain_pair_evals_per_s": pairs / (t_p * 1e-3),
+            "max_rel_diff_batched_vs_plain": err}
 
 
 if __name__ == "__main__":

@@ -148,29 +148,33 @@ static hipError_t launch_dr(int WS, bool sep, bool lagged, bool bary, const Laun
 template <int D>
 static hipError_t launch_d(const Schedule& sc, bool lagged, bool bary, const Launch& L, int nb,
                            hipStream_t s) {
-    hipError_t e;
     const bool sep = sc.sep != 0;
     switch (sc.R) {
-        case 1: e = launch_dr<D, 1>(sc.WS, sep, lagged, bary, L, nb, s); break;
-        case 2: e = launch_dr<D, 2>(sc.WS, sep, lagged, bary, L, nb, s); break;
-        case 4: e = launch_dr<D, 4>(sc.WS, sep, lagged, bary, L, nb, s); break;
-        default: e = launch_dr<D, 8>(sc.WS, sep, lagged, bary, L, nb, s); break;
+        case 1: return launch_dr<D, 1>(sc.WS, sep, lagged, bary, L, nb, s);
+        case 2: return launch_dr<D, 2>(sc.WS, sep, lagged, bary, L, nb, s);
+        case 4: return launch_dr<D, 4>(sc.WS, sep, lagged, bary, L, nb, s);
+        default: return launch_dr<D, 8>(sc.WS, sep, lagged, bary, L, nb, s);
     }
-    if (e != hipSuccess || !sep) return e;
-    return launch_merge<D>(sc.R, sc.WS, lagged, bary, L, s);
 }
 
+// One sweep: the sweep kernel, then (separate-merge schedules) the merge kernel.
+// With profiling on, each kernel gets its own event pair: kind4[0] is 0/1 for a
+// safe/lagged sweep and 10/11 for its merge.
 hipError_t launch_sweep(int d, const Schedule& sc, bool lagged, bool bary, const Launch& L,
                         int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
+    double pairs = 0.0;
+    for (int j = 0; j < L.njobs; ++j) pairs += (double)L.job[j].nq * L.job[j].nk;
+    const int code = sc.R * 100 + sc.WS * 10 + sc.sep;
     void* tok = profile_begin(s);
-    const hipError_t e = d == 2 ? launch_d<2>(sc, lagged, bary, L, nblocks, s)
-                                : launch_d<3>(sc, lagged, bary, L, nblocks, s);
-    if (tok) {
-        double pairs = 0.0;
-        for (int j = 0; j < L.njobs; ++j) pairs += (double)L.job[j].nq * L.job[j].nk;
-        profile_end(tok, s, lagged, bary, sc.R * 100 + sc.WS * 10 + sc.sep, nblocks, pairs);
-    }
+    hipError_t e = d == 2 ? launch_d<2>(sc, lagged, bary, L, nblocks, s)
+                          : launch_d<3>(sc, lagged, bary, L, nblocks, s);
+    if (tok) profile_end(tok, s, lagged, bary, code, nblocks, pairs);
+    if (e != hipSuccess || !sc.sep) return e;
+    tok = profile_begin(s);
+    e = d == 2 ? launch_merge<2>(sc.R, sc.WS, lagged, bary, L, s)
+               : launch_merge<3>(sc.R, sc.WS, lagged, bary, L, s);
+    if (tok) profile_end(tok, s, 10 + lagged, bary, code, 0, 0.0);
     return e;
 }
 
