@@ -79,6 +79,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the sweep schedules instead of loading the stored tuning table")
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the step captured into a HIP graph (replays)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -150,6 +152,28 @@ def main() -> int:
     ms = e0.elapsed_time(e1) / args.steps
     assert all(torch.isfinite(t).all().item() for t in out)
 
+    graph_ms = None
+    if args.graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gout = step()
+        graph.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / args.steps
+        assert all(torch.isfinite(t).all().item() for t in gout)
+        assert torch.allclose(gout[1], out[1], rtol=0, atol=0)
+
     sk_pairs = pairs_per_pass(T, M, K)
     svgd_pairs = T * T if use_svgd else 0
     total_pairs = sk_pairs + svgd_pairs
@@ -207,6 +231,7 @@ def main() -> int:
             "svgd_pairs": svgd_pairs,
             "tm_pair_evals_per_s": K * T * M / (ms * 1e-3),
             "schedules": tuned,
+            "graph_ms_per_step": graph_ms,
         },
         "roofline": {
             "bound": "alu",

@@ -25,6 +25,7 @@ CT_VALUE = 4
 CT_WARM_START = 8
 CT_REF_CACHED = 16
 CT_SAFE_LSE = 32
+CT_ONE_STREAM = 64
 
 CT_DYN_DOUBLE_INTEGRATOR = 0
 CT_DYN_UNICYCLE = 1

@@ -3,6 +3,8 @@
 // extrapolation pass and the reductions; the sweeps themselves are in sweep.hip.
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "ct_internal.h"
 
@@ -273,8 +275,8 @@ static SkLayout sk_layout(void* ws, int T, int M, int d) {
     return L;
 }
 
-static const uint32_t kKnownFlags =
-    CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_WARM_START | CT_REF_CACHED | CT_SAFE_LSE;
+static const uint32_t kKnownFlags = CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_WARM_START |
+                                    CT_REF_CACHED | CT_SAFE_LSE | CT_ONE_STREAM;
 
 static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
                           const ct_sinkhorn_opts* o) {
@@ -418,6 +420,23 @@ static void iteration_sets(const SkJobs& J, int cur, bool debias, bool ref_iter,
     }
 }
 
+// One auxiliary stream per device (default priority, non-blocking), created on first use.
+static ct_status aux_stream(hipStream_t* out) {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    CT_CHECK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(dev);
+    if (it == streams.end()) {
+        hipStream_t s;
+        CT_CHECK_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        it = streams.emplace(dev, s).first;
+    }
+    *out = it->second;
+    return CT_OK;
+}
+
 // Iterate-and-extrapolate for one problem whose arrays are staged in L.
 static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_opts* o,
                              hipStream_t st) {
@@ -433,16 +452,55 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     const Schedule sA = schedule_for(d, T, M);
     const Schedule sB = schedule_for(d, M, T);
 
+    const bool any_self = debias || ref_iter;
+    const bool two_streams = any_self && o->iters > 0 && !(o->flags & CT_ONE_STREAM);
     int cur = 0;  // which ping-pong self record array is current
-    for (int k = 0; k < o->iters; ++k) {
-        const bool lagged = !safe_only && (warm || k > 0);
-        JobSet A, B;
-        iteration_sets(J, cur, debias, ref_iter, A, B);
-        ct_status rc = launch_set(A, c, sA, lagged, false, st);
+    if (two_streams) {
+        // the self problems do not depend on f and g: run their K sweeps on the
+        // auxiliary stream while the cross sweeps run on `st`
+        hipStream_t aux = nullptr;
+        ct_status rc = aux_stream(&aux);
         if (rc) return rc;
-        rc = launch_set(B, c, sB, lagged, false, st);
-        if (rc) return rc;
-        cur ^= 1;
+        hipEvent_t fork, join;
+        CT_CHECK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        CT_CHECK_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        CT_CHECK_HIP(hipEventRecord(fork, st));
+        CT_CHECK_HIP(hipStreamWaitEvent(aux, fork, 0));
+        const Schedule sS = schedule_for(d, ref_iter ? M : T, ref_iter ? M : T);
+        for (int k = 0; k < o->iters; ++k) {
+            const bool lagged = !safe_only && (warm || k > 0);
+            JobSet Sf;
+            if (debias) Sf.add(J.p(cur, true, L.p, L.xrec[2 + (cur ^ 1)], nullptr));
+            if (ref_iter) Sf.add(J.q(cur, true, L.q, L.yrec[1 + (cur ^ 1)]));
+            rc = launch_set(Sf, c, sS, lagged, false, aux);
+            if (rc) return rc;
+            cur ^= 1;
+        }
+        for (int k = 0; k < o->iters; ++k) {
+            const bool lagged = !safe_only && (warm || k > 0);
+            JobSet A, B;
+            A.add(J.f(L.f, L.xrec[0], nullptr));
+            B.add(J.g(L.xrec[0], L.g, L.yrec[0]));
+            rc = launch_set(A, c, sA, lagged, false, st);
+            if (rc) return rc;
+            rc = launch_set(B, c, sB, lagged, false, st);
+            if (rc) return rc;
+        }
+        CT_CHECK_HIP(hipEventRecord(join, aux));
+        CT_CHECK_HIP(hipStreamWaitEvent(st, join, 0));
+        CT_CHECK_HIP(hipEventDestroy(fork));
+        CT_CHECK_HIP(hipEventDestroy(join));
+    } else {
+        for (int k = 0; k < o->iters; ++k) {
+            const bool lagged = !safe_only && (warm || k > 0);
+            JobSet A, B;
+            iteration_sets(J, cur, debias, ref_iter, A, B);
+            ct_status rc = launch_set(A, c, sA, lagged, false, st);
+            if (rc) return rc;
+            rc = launch_set(B, c, sB, lagged, false, st);
+            if (rc) return rc;
+            cur ^= 1;
+        }
     }
     const bool lagged_final = !safe_only && (warm || o->iters > 0);
     {
@@ -663,10 +721,16 @@ extern "C" ct_status ct_autotune_sinkhorn(int64_t T64, int64_t M64, const ct_sin
     const SkJobs J{L, c};
     const bool debias = o->flags & CT_DEBIAS;
     const bool ref_iter = debias && (o->flags & (CT_VALUE | CT_GRAD_W));
-    JobSet A, B;
-    iteration_sets(J, 0, debias, ref_iter, A, B);
-    for (int side = 0; side < 2; ++side) {
-        const JobSet& S = side == 0 ? A : B;
+    // the launches of the default (two-stream) schedule: cross f, cross g, self p + q
+    JobSet sets[3];
+    sets[0].add(J.f(L.f, L.xrec[0], nullptr));
+    sets[1].add(J.g(L.xrec[0], L.g, L.yrec[0]));
+    if (debias) sets[2].add(J.p(0, true, L.p, L.xrec[3], nullptr));
+    if (ref_iter) sets[2].add(J.q(0, true, L.q, L.yrec[2]));
+    const int keys[3][2] = {{T, M}, {M, T}, {ref_iter ? M : T, ref_iter ? M : T}};
+    for (int side = 0; side < 3; ++side) {
+        const JobSet& S = sets[side];
+        if (S.n == 0) continue;
         float best = 1e30f;
         Schedule bs = cand[0];
         for (int ci = 0; ci < nc; ++ci) {
@@ -688,8 +752,7 @@ extern "C" ct_status ct_autotune_sinkhorn(int64_t T64, int64_t M64, const ct_sin
                 bs = cand[ci];
             }
         }
-        if (side == 0) tuning_record(d, T, M, bs, (int)(best * 1000.f + 0.5f));
-        else tuning_record(d, M, T, bs, (int)(best * 1000.f + 0.5f));
+        tuning_record(d, keys[side][0], keys[side][1], bs, (int)(best * 1000.f + 0.5f));
     }
     CT_CHECK_HIP(hipEventDestroy(e0));
     CT_CHECK_HIP(hipEventDestroy(e1));

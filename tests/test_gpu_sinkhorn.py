@@ -156,3 +156,35 @@ def test_every_schedule_matches_oracle(ct, tmp_path, R, WS, bpc, sep):
         ct.tuning_clear()
     r = _oracle(x, y, w, eps, iters)
     _compare(g, r, T, M, w)
+
+
+def test_one_stream_and_two_streams_agree(ct):
+    """The self sweeps on the auxiliary stream (default) give the same bits as all
+    sweeps on the caller's stream."""
+    from paper_2511_11514_amd import _lib
+    import ctypes
+    x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=1200, M=2500)
+    dev = torch.device("cuda")
+    t = lambda a: torch.as_tensor(a, device=dev)
+    outs = []
+    xt, yt, wt = t(x), t(y), t(w)
+    for extra in (0, _lib.CT_ONE_STREAM):
+        T, M, d = 1200, 2500, 2
+        flags = _lib.CT_DEBIAS | _lib.CT_VALUE | _lib.CT_GRAD_W | extra
+        o = _lib.SinkhornOpts(d, 30, 0.01, flags)
+        gx = torch.empty(T, d, device=dev)
+        gw = torch.empty(M, device=dev)
+        val = torch.empty(1, device=dev)
+        nb = _lib.lib().ct_sinkhorn_workspace_size(T, M, ctypes.byref(o))
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        P = lambda z: ctypes.c_void_p(z.data_ptr())
+        st = _lib.lib().ct_sinkhorn_grad(P(xt), T, P(yt), P(wt), M, ctypes.byref(o), P(gx),
+                                         P(gw), P(val), None, None, None, P(ws), nb,
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == 0
+        torch.cuda.synchronize()
+        outs.append((gx.cpu(), gw.cpu(), val.cpu()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    r = _oracle(x, y, w, 0.01, 30)
+    assert rel(outs[0][0].numpy(), r.grad_x) < TOL
