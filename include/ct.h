@@ -70,10 +70,10 @@ const char* ct_version(void);
 #define CT_WARM_START 8u  /* start from the potentials in `pot` instead of zeros */
 #define CT_REF_CACHED 16u /* `pot` holds a converged reference self potential q: skip its iterations */
 #define CT_SAFE_LSE 32u   /* track the running maximum in every sweep (no lagged shift) */
-#define CT_ONE_STREAM 64u /* keep the self-problem sweeps on `stream` (default: they run on a
-                             library-owned auxiliary stream of the current device, forked from and
-                             joined back into `stream` with events, so they overlap the cross
-                             sweeps; the fork/join is graph-capture compatible) */
+#define CT_ONE_STREAM 64u /* serialise every sweep on `stream` (default: the self-problem sweeps
+                             run on a library-owned auxiliary stream of the current device, forked
+                             from and joined back into `stream` with events, so they overlap the
+                             cross sweeps; the fork/join is graph-capture compatible) */
 
 typedef struct ct_sinkhorn_opts {
     int32_t d;      /* 2 or 3 */

@@ -66,7 +66,8 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
                   eps: float, iters: int, debias: bool = True, value: bool = False,
                   grad_w: bool = False, init: Optional[torch.Tensor] = None,
                   ref_q: Optional[torch.Tensor] = None, safe: bool = False,
-                  potentials: bool = False, aux: bool = False) -> SinkhornOut:
+                  potentials: bool = False, aux: bool = False,
+                  one_stream: bool = False) -> SinkhornOut:
     """Gradient of the (debiased) Sinkhorn divergence; see ct_sinkhorn_grad.
 
     x [T,d], y [M,d], w [M] or None: float32 GPU tensors.
@@ -83,7 +84,8 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
     if y.shape[1] != d:
         raise ValueError("x and y must have the same dimension")
     flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
-        (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0)
+        (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
+        (L.CT_ONE_STREAM if one_stream else 0)
     pot = None
     if init is not None or ref_q is not None or potentials:
         pot = torch.zeros(2 * T + 2 * M, dtype=torch.float32, device=dev)
@@ -114,10 +116,12 @@ class SinkhornDivergence(torch.autograd.Function):
     only scales them by the incoming gradient, so no second solve is needed."""
 
     @staticmethod
-    def forward(ctx, x, y, w, eps: float, iters: int, debias: bool = True):
+    def forward(ctx, x, y, w, eps: float, iters: int, debias: bool = True,
+                one_stream: bool = False):
         need_w = bool(w is not None and ctx.needs_input_grad[2])
         out = sinkhorn_grad(x.detach(), y.detach(), None if w is None else w.detach(), eps=eps,
-                            iters=iters, debias=debias, value=True, grad_w=need_w)
+                            iters=iters, debias=debias, value=True, grad_w=need_w,
+                            one_stream=one_stream)
         ctx.save_for_backward(out.grad_x, out.grad_w if need_w else None)
         ctx.need_w = need_w
         return out.value.reshape(())
@@ -126,11 +130,12 @@ class SinkhornDivergence(torch.autograd.Function):
     @once_differentiable
     def backward(ctx, gS):
         gx, gw = ctx.saved_tensors
-        return gS * gx, None, (gS * gw if ctx.need_w else None), None, None, None
+        return gS * gx, None, (gS * gw if ctx.need_w else None), None, None, None, None
 
 
-def sinkhorn_divergence(x, y, w=None, *, eps: float, iters: int, debias: bool = True):
-    return SinkhornDivergence.apply(x, y, w, eps, iters, debias)
+def sinkhorn_divergence(x, y, w=None, *, eps: float, iters: int, debias: bool = True,
+                        one_stream: bool = False):
+    return SinkhornDivergence.apply(x, y, w, eps, iters, debias, one_stream)
 
 
 @dataclass

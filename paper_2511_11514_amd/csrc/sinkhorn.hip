@@ -321,18 +321,6 @@ struct JobSet {
     }
 };
 
-// The job restricted to queries [q0, q0 + n).
-static Job sub_job(Job j, int q0, int n, int d) {
-    j.qrec += q0;
-    j.qpot += q0;
-    if (j.qlog2w) j.qlog2w += q0;
-    j.out_pot += q0;
-    if (j.out_rec) j.out_rec += q0;
-    if (j.out_bary) j.out_bary += (size_t)q0 * d;
-    j.nq = n;
-    return j;
-}
-
 static ct_status launch_set(const JobSet& js, const SkConsts& c, const Schedule& sc, bool lagged,
                             bool bary, hipStream_t st) {
     if (js.n == 0) return CT_OK;
@@ -397,29 +385,6 @@ struct SkJobs {
     }
 };
 
-// The two launches of one Sinkhorn iteration.  Launch A updates f (Gauss-Seidel
-// half-step); launch B updates g from the new f.  The self problems do not
-// depend on f and g, so each averaged self update is split by queries: the
-// first half runs beside f, the second beside g (both halves read the previous
-// self records, write the other ping-pong buffer, and update disjoint entries),
-// which balances the two launches.
-static void iteration_sets(const SkJobs& J, int cur, bool debias, bool ref_iter, JobSet& A,
-                           JobSet& B) {
-    const int T = J.c.T, M = J.c.M, d = J.c.d;
-    A.add(J.f(J.L.f, J.L.xrec[0], nullptr));
-    B.add(J.g(J.L.xrec[0], J.L.g, J.L.yrec[0]));
-    if (debias) {
-        const Job jp = J.p(cur, true, J.L.p, J.L.xrec[2 + (cur ^ 1)], nullptr);
-        A.add(sub_job(jp, 0, T / 2, d));
-        B.add(sub_job(jp, T / 2, T - T / 2, d));
-    }
-    if (ref_iter) {
-        const Job jq = J.q(cur, true, J.L.q, J.L.yrec[1 + (cur ^ 1)]);
-        A.add(sub_job(jq, 0, M / 2, d));
-        B.add(sub_job(jq, M / 2, M - M / 2, d));
-    }
-}
-
 // One auxiliary stream per device (default priority, non-blocking), created on first use.
 static ct_status aux_stream(hipStream_t* out) {
     static std::mutex mu;
@@ -452,55 +417,50 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     const Schedule sA = schedule_for(d, T, M);
     const Schedule sB = schedule_for(d, M, T);
 
+    // The self problems do not depend on f and g: their K sweeps run on the
+    // auxiliary stream (forked from / joined back into `st` with events) while the
+    // cross sweeps run on `st`; with CT_ONE_STREAM the same launches are serialised
+    // on `st`.
     const bool any_self = debias || ref_iter;
     const bool two_streams = any_self && o->iters > 0 && !(o->flags & CT_ONE_STREAM);
-    int cur = 0;  // which ping-pong self record array is current
+    hipStream_t sst = st;
+    hipEvent_t fork = nullptr, join = nullptr;
     if (two_streams) {
-        // the self problems do not depend on f and g: run their K sweeps on the
-        // auxiliary stream while the cross sweeps run on `st`
-        hipStream_t aux = nullptr;
-        ct_status rc = aux_stream(&aux);
+        ct_status rc = aux_stream(&sst);
         if (rc) return rc;
-        hipEvent_t fork, join;
         CT_CHECK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
         CT_CHECK_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
         CT_CHECK_HIP(hipEventRecord(fork, st));
-        CT_CHECK_HIP(hipStreamWaitEvent(aux, fork, 0));
+        CT_CHECK_HIP(hipStreamWaitEvent(sst, fork, 0));
+    }
+    int cur = 0;  // which ping-pong self record array is current
+    if (any_self) {
         const Schedule sS = schedule_for(d, ref_iter ? M : T, ref_iter ? M : T);
         for (int k = 0; k < o->iters; ++k) {
             const bool lagged = !safe_only && (warm || k > 0);
             JobSet Sf;
             if (debias) Sf.add(J.p(cur, true, L.p, L.xrec[2 + (cur ^ 1)], nullptr));
             if (ref_iter) Sf.add(J.q(cur, true, L.q, L.yrec[1 + (cur ^ 1)]));
-            rc = launch_set(Sf, c, sS, lagged, false, aux);
+            ct_status rc = launch_set(Sf, c, sS, lagged, false, sst);
             if (rc) return rc;
             cur ^= 1;
         }
-        for (int k = 0; k < o->iters; ++k) {
-            const bool lagged = !safe_only && (warm || k > 0);
-            JobSet A, B;
-            A.add(J.f(L.f, L.xrec[0], nullptr));
-            B.add(J.g(L.xrec[0], L.g, L.yrec[0]));
-            rc = launch_set(A, c, sA, lagged, false, st);
-            if (rc) return rc;
-            rc = launch_set(B, c, sB, lagged, false, st);
-            if (rc) return rc;
-        }
-        CT_CHECK_HIP(hipEventRecord(join, aux));
+    }
+    for (int k = 0; k < o->iters; ++k) {
+        const bool lagged = !safe_only && (warm || k > 0);
+        JobSet A, B;
+        A.add(J.f(L.f, L.xrec[0], nullptr));
+        B.add(J.g(L.xrec[0], L.g, L.yrec[0]));
+        ct_status rc = launch_set(A, c, sA, lagged, false, st);
+        if (rc) return rc;
+        rc = launch_set(B, c, sB, lagged, false, st);
+        if (rc) return rc;
+    }
+    if (two_streams) {
+        CT_CHECK_HIP(hipEventRecord(join, sst));
         CT_CHECK_HIP(hipStreamWaitEvent(st, join, 0));
         CT_CHECK_HIP(hipEventDestroy(fork));
         CT_CHECK_HIP(hipEventDestroy(join));
-    } else {
-        for (int k = 0; k < o->iters; ++k) {
-            const bool lagged = !safe_only && (warm || k > 0);
-            JobSet A, B;
-            iteration_sets(J, cur, debias, ref_iter, A, B);
-            ct_status rc = launch_set(A, c, sA, lagged, false, st);
-            if (rc) return rc;
-            rc = launch_set(B, c, sB, lagged, false, st);
-            if (rc) return rc;
-            cur ^= 1;
-        }
     }
     const bool lagged_final = !safe_only && (warm || o->iters > 0);
     {
