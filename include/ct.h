@@ -267,21 +267,27 @@ ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, const float* 
 /* ------------------------------------------------------------------------- */
 
 /*
- * Times the candidate schedules (queries per lane, blocks per CU) of the
- * Sinkhorn sweep kernel for this problem shape on `stream` (synchronously) and
- * records the fastest in the process-wide tuning table, keyed by (d, size
- * class of T, size class of M).  Later ct_sinkhorn_grad / _batched calls of
- * that class use it.  `ws` must hold ct_sinkhorn_workspace_size(T, M, o) bytes.
- * Must not be called while `stream` is being captured.
+ * Times the candidate schedules of the Sinkhorn sweep kernel (queries per lane,
+ * key-splitting waves per block, blocks per CU, merge by a separate kernel or by
+ * the last block) for the three launch sets of this problem shape (cross f, cross g, self p + q) on
+ * `stream` (synchronously), and records the fastest of each in the process-wide
+ * tuning table, keyed by (d, size class of the query set, size class of the key
+ * set).  Later ct_sinkhorn_grad calls of those classes use them.  `ws` must hold
+ * ct_sinkhorn_workspace_size(T, M, o) bytes.  Must not be called while `stream`
+ * is being captured.
  */
 ct_status ct_autotune_sinkhorn(int64_t T, int64_t M, const ct_sinkhorn_opts* o, void* ws,
                                size_t ws_bytes, void* stream);
-/* Number of tuned entries, and entry i as (d, query-set size class, key-set size
- * class, queries per lane, key-splitting waves per block, blocks per CU, time in
- * microseconds of one sweep); a size class is ceil(log2(n)). */
+/* Number of tuned entries, and entry i written to out8 (host, 8 ints) as
+ * (d, query-set size class, key-set size class, queries per lane, key-splitting
+ * waves per block, blocks per CU, separate merge 0/1, time in microseconds of
+ * one sweep); a size class is ceil(log2(n)).  CT_E_ARG for an index out of range
+ * or a null out8. */
 int32_t ct_tuning_count(void);
-ct_status ct_tuning_entry(int32_t i, int32_t* out7);
-/* Save / load the tuning table as text (one entry per line). */
+ct_status ct_tuning_entry(int32_t i, int32_t* out8);
+/* Save / load the tuning table as text, one entry per line with the eight fields
+ * of ct_tuning_entry in that order ('#' starts a comment line).  Loading merges
+ * into the table; a malformed line fails with CT_E_ARG. */
 ct_status ct_tuning_save(const char* path);
 ct_status ct_tuning_load(const char* path);
 void ct_tuning_clear(void);
@@ -293,15 +299,36 @@ void ct_tuning_clear(void);
 /*
  * While enabled, every sweep-kernel launch is bracketed by a pair of HIP events
  * recorded on its stream (adds two event records per launch; do not enable while
- * capturing a graph).  Record i gives (kind4 = {lagged shift, offsets pass,
- * 100 * queries per lane + 10 * key-splitting waves, blocks}, the launch's point
- * pairs, its elapsed ms);
+ * capturing a graph).  Record i gives (kind4 = {0 / 1 for a tracked-maximum /
+ * lagged-shift sweep, or 10 / 11 for the merge kernel that follows it; offsets
+ * pass 0/1; 100 * queries per lane + 10 * key-splitting waves + separate merge;
+ * blocks}, the launch's point pairs (0 for a merge), its elapsed ms);
  * ct_profile_read waits for the record's end event.
  */
 ct_status ct_profile_enable(int32_t on);
 int32_t ct_profile_count(void);
 ct_status ct_profile_read(int32_t i, int32_t* kind4, double* pairs, float* ms);
 void ct_profile_clear(void);
+
+/* ------------------------------------------------------------------------- */
+/* Issue-rate probe (measurement support for the sweep roofline)                */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * The sweeps are bound by plain vector-ALU issue: per point pair d subtractions,
+ * d FMAs, one more subtraction, one v_exp_f32 and one add.  Public figures give
+ * only the packed-FMA peak, so the per-instruction rates are measured here: five
+ * timed launches on `stream` (synchronous; not while capturing) of 2048 blocks x
+ * 256 threads, each lane running 8 independent chains of 2048 steps.  out6 (host)
+ * receives lanes per clock per CU of v_add_f32 [0], v_fma_f32 [1] and v_exp_f32
+ * [2]; FMAs per clock per CU of v_mfma_f32_16x16x4f32 [3]; the time of MFMA and
+ * exp chains issued by the same waves divided by the sum of their separate times
+ * [4] (1: the matrix cores and the vector ALU do not overlap, 0.5: they fully
+ * overlap); and the clock used, the device's reported peak, in Hz [5].
+ * ws: device scratch of ct_probe_workspace_size() bytes (clobbered).
+ */
+size_t ct_probe_workspace_size(void);
+ct_status ct_probe_alu_rates(double* out6, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

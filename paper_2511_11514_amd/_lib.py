@@ -92,6 +92,8 @@ _SIGS = {
     "ct_profile_count": (c_int32, []),
     "ct_profile_read": (c_int32, [c_int32, POINTER(c_int32), PD, POINTER(c_float)]),
     "ct_profile_clear": (None, []),
+    "ct_probe_workspace_size": (c_size_t, []),
+    "ct_probe_alu_rates": (c_int32, [PD, P, c_size_t, P]),
 }
 
 

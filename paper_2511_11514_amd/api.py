@@ -348,10 +348,24 @@ def autotune_sinkhorn(T: int, M: int, d: int, eps: float, device="cuda") -> None
     check("ct_autotune_sinkhorn", st)
 
 
+def probe_alu_rates(device="cuda") -> dict:
+    """Measured issue rates of the instructions that bound the sweeps (see
+    ct_probe_alu_rates): lanes per clock per CU of add, FMA and exp2, MFMA FP32
+    FMAs per clock per CU, the MFMA/exp overlap ratio and the clock in Hz."""
+    dev = torch.device(device)
+    n = lib().ct_probe_workspace_size()
+    ws = _workspace(n, dev)
+    out = (ctypes.c_double * 6)()
+    check("ct_probe_alu_rates", lib().ct_probe_alu_rates(out, _p(ws), n, _stream(dev)))
+    keys = ("add", "fma", "exp", "mfma_f32", "mfma_exp_overlap", "clock_hz")
+    return dict(zip(keys, list(out)))
+
+
 def tuning_table():
+    """Entries (d, qclass, kclass, R, WS, blocks_per_cu, sep, us)."""
     n = lib().ct_tuning_count()
     out = []
-    buf = (ctypes.c_int32 * 7)()
+    buf = (ctypes.c_int32 * 8)()
     for i in range(n):
         check("ct_tuning_entry", lib().ct_tuning_entry(i, buf))
         out.append(tuple(buf))

@@ -41,6 +41,41 @@ __global__ __launch_bounds__(1024) void k_wsum(const float* __restrict__ w, int 
     if (threadIdx.x == 0) *out = red[0];
 }
 
+// Common origin of both point sets (mean of every coordinate, double, fixed
+// order, non-finite values skipped).  The soft-min is translation invariant, but
+// the float32 prescale x * sqrt(kappa) is not: far from the coordinate origin it
+// would round away the low bits of every difference x_i - y_j.  Subtracting the
+// origin first (exact for nearby float32 values) keeps them.
+__global__ __launch_bounds__(1024) void k_origin(const float* __restrict__ x, int T,
+                                                 const float* __restrict__ y, int M, int d,
+                                                 float* __restrict__ out) {
+    __shared__ double red[3][1024];
+    __shared__ double cnt[1024];
+    double s[3] = {0.0, 0.0, 0.0}, n = 0.0;
+    for (int i = threadIdx.x; i < T + M; i += 1024) {
+        const float* p = i < T ? x + (size_t)i * d : y + (size_t)(i - T) * d;
+        bool ok = true;
+        for (int t = 0; t < d; ++t) ok = ok && isfinite(p[t]);
+        if (!ok) continue;
+        for (int t = 0; t < d; ++t) s[t] += (double)p[t];
+        n += 1.0;
+    }
+    for (int t = 0; t < 3; ++t) red[t][threadIdx.x] = s[t];
+    cnt[threadIdx.x] = n;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            for (int t = 0; t < 3; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + h];
+            cnt[threadIdx.x] += cnt[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) {
+        const double c = cnt[0] > 0.0 ? cnt[0] : 1.0;
+        out[threadIdx.x] = (int)threadIdx.x < d ? (float)(red[threadIdx.x][0] / c) : 0.f;
+    }
+}
+
 struct StageArgs {
     const float* x;
     const float* y;
@@ -50,6 +85,7 @@ struct StageArgs {
     int T, M, d, Tpad, Mpad;
     float sqrt_kappa, kappa, log2a;
     const double* wsum;
+    const float* origin;     // [3] subtracted before scaling
     float4* cx;              // query coordinates of x
     float4* cy;              // query coordinates of y
     float4* xrec[4];         // key records of x: f (g-sweeps), f+ (g+ sweep), p ping-pong
@@ -77,7 +113,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A) {
             for (int t = 0; t < A.d; ++t) {
                 const float v = A.x[(size_t)i * A.d + t];
                 bad |= !isfinite(v);
-                c[t] = v * A.sqrt_kappa;
+                c[t] = (v - A.origin[t]) * A.sqrt_kappa;
             }
             A.cx[i] = make_float4(c[0], c[1], c[2], 0.f);
             const float f0 = A.warm ? A.pot_in[i] : 0.f;
@@ -102,7 +138,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A) {
             for (int t = 0; t < A.d; ++t) {
                 const float v = A.y[(size_t)i * A.d + t];
                 bad |= !isfinite(v);
-                c[t] = v * A.sqrt_kappa;
+                c[t] = (v - A.origin[t]) * A.sqrt_kappa;
             }
             A.cy[i] = make_float4(c[0], c[1], c[2], 0.f);
             const float wj = A.w ? A.w[i] : 1.f;
@@ -232,6 +268,7 @@ struct SkLayout {
     float4* cy;
     float4* xrec[4];         // 0: h from f (keys of g-sweeps), 1: from f+, 2/3: from p (ping-pong)
     float4* yrec[3];         // 0: h from g (keys of f-sweeps), 1/2: from q (ping-pong)
+    float* origin;           // [4] common origin subtracted before scaling
     float* b;
     float* log2b;
     float *f, *g, *p, *q;
@@ -254,6 +291,7 @@ static SkLayout sk_layout(void* ws, int T, int M, int d) {
     L.cy = a.take<float4>(M);
     for (int r = 0; r < 4; ++r) L.xrec[r] = a.take<float4>(Tp);
     for (int r = 0; r < 3; ++r) L.yrec[r] = a.take<float4>(Mp);
+    L.origin = a.take<float>(4);
     L.b = a.take<float>(M);
     L.log2b = a.take<float>(M);
     L.f = a.take<float>(T);
@@ -529,6 +567,8 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
     }
     hipLaunchKernelGGL(k_wsum, dim3(1), dim3(1024), 0, st, w, M, L.wsum);
     CT_CHECK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_origin, dim3(1), dim3(1024), 0, st, x, T, y, M, d, L.origin);
+    CT_CHECK_HIP(hipGetLastError());
     StageArgs A;
     A.x = x; A.y = y; A.w = w; A.pot_in = pot;
     A.warm = (o->flags & CT_WARM_START) ? 1 : 0;
@@ -537,7 +577,7 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
     A.sqrt_kappa = (float)std::sqrt(kappa_d);
     A.kappa = (float)kappa_d;
     A.log2a = (float)(-std::log2((double)T));
-    A.wsum = L.wsum; A.cx = L.cx; A.cy = L.cy; A.b = L.b; A.log2b = L.log2b;
+    A.wsum = L.wsum; A.origin = L.origin; A.cx = L.cx; A.cy = L.cy; A.b = L.b; A.log2b = L.log2b;
     A.f = L.f; A.g = L.g; A.p = L.p; A.q = L.q;
     for (int r = 0; r < 4; ++r) A.xrec[r] = L.xrec[r];
     for (int r = 0; r < 3; ++r) A.yrec[r] = L.yrec[r];

@@ -1,5 +1,6 @@
-// Process-wide tuning table for the sweep schedule (queries per lane, blocks
-// per CU), keyed by (d, size class of the query set, size class of the key set).
+// Process-wide tuning table for the sweep schedule (queries per lane, key-splitting
+// waves, blocks per CU, merge mode), keyed by (d, size class of the query set,
+// size class of the key set).
 #include <cstdio>
 #include <map>
 #include <mutex>
@@ -50,7 +51,8 @@ bool tuning_lookup(int d, int qclass, int kclass, Schedule& out) {
 
 void tuning_record(int d, int64_t nq, int64_t nk, const Schedule& sc, int us) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_table[{d, size_class(nq), size_class(nk)}] = Entry{sc.R, sc.WS, sc.blocks_per_cu, sc.sep, us};
+    g_table[{d, size_class(nq), size_class(nk)}] =
+        Entry{sc.R, sc.WS, sc.blocks_per_cu, sc.sep, us};
 }
 
 }  // namespace ct
@@ -62,19 +64,20 @@ extern "C" int32_t ct_tuning_count(void) {
     return (int32_t)g_table.size();
 }
 
-extern "C" ct_status ct_tuning_entry(int32_t i, int32_t* out7) {
-    if (!out7) return fail(CT_E_ARG, "out7 is null");
+extern "C" ct_status ct_tuning_entry(int32_t i, int32_t* out8) {
+    if (!out8) return fail(CT_E_ARG, "out8 is null");
     std::lock_guard<std::mutex> lk(g_mu);
     if (i < 0 || i >= (int32_t)g_table.size()) return fail(CT_E_ARG, "entry %d out of range", i);
     auto it = g_table.begin();
     std::advance(it, i);
-    out7[0] = std::get<0>(it->first);
-    out7[1] = std::get<1>(it->first);
-    out7[2] = std::get<2>(it->first);
-    out7[3] = it->second.R;
-    out7[4] = it->second.WS;
-    out7[5] = it->second.bpc * 10 + it->second.sep;
-    out7[6] = it->second.us;
+    out8[0] = std::get<0>(it->first);
+    out8[1] = std::get<1>(it->first);
+    out8[2] = std::get<2>(it->first);
+    out8[3] = it->second.R;
+    out8[4] = it->second.WS;
+    out8[5] = it->second.bpc;
+    out8[6] = it->second.sep;
+    out8[7] = it->second.us;
     return CT_OK;
 }
 
@@ -101,9 +104,10 @@ extern "C" ct_status ct_tuning_load(const char* path) {
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         int d, qc, kc, R, ws, b, sep, us;
-        if (std::sscanf(line, "%d %d %d %d %d %d %d %d", &d, &qc, &kc, &R, &ws, &b, &sep, &us) != 8)
-            continue;
-        if ((d != 2 && d != 3) || (R != 1 && R != 2 && R != 4 && R != 8) ||
+        const int nf = std::sscanf(line, "%d %d %d %d %d %d %d %d", &d, &qc, &kc, &R, &ws, &b,
+                                   &sep, &us);
+        if (nf <= 0) continue;  // blank line
+        if (nf != 8 || (d != 2 && d != 3) || (R != 1 && R != 2 && R != 4 && R != 8) ||
             (ws != 1 && ws != 2 && ws != 4) || b < 1 || b > 16 || (sep != 0 && sep != 1)) {
             std::fclose(f);
             return fail(CT_E_ARG, "bad tuning entry: %s", line);

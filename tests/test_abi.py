@@ -74,3 +74,36 @@ def test_workspace_size_is_monotone_and_rejects_bad_shapes():
     assert L.ct_sinkhorn_workspace_size(0, 10, ctypes.byref(o)) == 0
     bad = _lib.SinkhornOpts(5, 10, 0.01, 1)
     assert L.ct_sinkhorn_workspace_size(10, 10, ctypes.byref(bad)) == 0
+
+
+def test_tuning_table_round_trip_and_validation(tmp_path):
+    """The tuning table text format: eight fields per entry, read back through
+    ct_tuning_entry and ct_tuning_save; malformed lines are rejected."""
+    import paper_2511_11514_amd as ct
+    from paper_2511_11514_amd import _lib
+    ct.tuning_clear()
+    try:
+        f = tmp_path / "t.txt"
+        f.write_text("# comment\n2 12 14 2 4 8 1 17\n\n3 14 16 4 2 16 0 123\n")
+        ct.tuning_load(str(f))
+        assert sorted(ct.tuning_table()) == [(2, 12, 14, 2, 4, 8, 1, 17),
+                                             (3, 14, 16, 4, 2, 16, 0, 123)]
+        g = tmp_path / "g.txt"
+        ct.tuning_save(str(g))
+        ct.tuning_clear()
+        assert ct.tuning_table() == []
+        ct.tuning_load(str(g))
+        assert len(ct.tuning_table()) == 2
+        for bad in ("2 12 14 2 4 8 17\n",          # seven fields
+                    "2 12 14 3 4 8 1 17\n",        # R = 3
+                    "2 12 14 2 3 8 1 17\n",        # WS = 3
+                    "2 12 14 2 4 32 1 17\n",       # 32 blocks per CU
+                    "4 12 14 2 4 8 1 17\n"):       # d = 4
+            h = tmp_path / "bad.txt"
+            h.write_text(bad)
+            with pytest.raises(_lib.CtError):
+                ct.tuning_load(str(h))
+        buf = (ctypes.c_int32 * 8)()
+        assert _lib.lib().ct_tuning_entry(99, buf) == _lib.CT_E_ARG
+    finally:
+        ct.tuning_clear()

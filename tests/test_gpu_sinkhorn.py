@@ -139,22 +139,45 @@ def _size_class(n):
     return c
 
 
+def _force_schedule(ct, tmp_path, d, T, M, R, WS, bpc, sep):
+    """Load a tuning table that gives every launch set of (T, M) this schedule."""
+    f = tmp_path / "tune.txt"
+    cT, cM = _size_class(T), _size_class(M)
+    f.write_text("".join(f"{d} {a} {b} {R} {WS} {bpc} {sep} 0\n"
+                         for a, b in ((cT, cM), (cM, cT), (cT, cT), (cM, cM))))
+    ct.tuning_clear()
+    ct.tuning_load(str(f))
+
+
 @pytest.mark.parametrize("R,WS,bpc,sep", [(1, 1, 2, 0), (2, 4, 8, 0), (4, 2, 16, 0), (8, 1, 1, 0),
                                           (1, 4, 16, 1), (2, 2, 4, 1), (4, 1, 8, 1), (8, 4, 2, 1)])
 def test_every_schedule_matches_oracle(ct, tmp_path, R, WS, bpc, sep):
-    """Each tile/split/merge schedule the tuner may pick gives the same result."""
+    """Each tile/split/merge schedule the tuner may pick, for the cross and the
+    self launch sets, gives the same result."""
     d, T, M, eps, iters = 2, 1500, 2100, 0.01, 15
     x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=T, M=M)
-    f = tmp_path / "tune.txt"
-    cT, cM = _size_class(T), _size_class(M)
-    f.write_text(f"{d} {cT} {cM} {R} {WS} {bpc} {sep} 0\n{d} {cM} {cT} {R} {WS} {bpc} {sep} 0\n")
-    ct.tuning_clear()
-    ct.tuning_load(str(f))
+    _force_schedule(ct, tmp_path, d, T, M, R, WS, bpc, sep)
     try:
         g = _run(ct, x, y, w, eps, iters)
     finally:
         ct.tuning_clear()
     r = _oracle(x, y, w, eps, iters)
+    _compare(g, r, T, M, w)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_far_from_coordinate_origin(ct, d):
+    """Point sets far from the coordinate origin: the staged coordinates are
+    centred before the sqrt(kappa) prescale, so no low bits of the differences
+    are lost and the result matches the oracle at the same bar."""
+    T, M, eps, iters = 900, 1300, 0.01, 20
+    name = "autograd_3d" if d == 3 else "grad_2d"
+    x, y, w, _g = W.config_inputs(W.CONFIGS[name], T=T, M=M)
+    shift = np.array([250.0, -125.0, 60.0][:d])
+    xs = (x.astype(np.float64) + shift).astype(np.float32)
+    ys = (y.astype(np.float64) + shift).astype(np.float32)
+    g = _run(ct, xs, ys, w, eps, iters)
+    r = _oracle(xs.astype(np.float64), ys.astype(np.float64), w, eps, iters)
     _compare(g, r, T, M, w)
 
 
