@@ -107,3 +107,15 @@ def test_tuning_table_round_trip_and_validation(tmp_path):
         assert _lib.lib().ct_tuning_entry(99, buf) == _lib.CT_E_ARG
     finally:
         ct.tuning_clear()
+
+
+def test_probe_rejects_bad_arguments_before_launch():
+    from paper_2511_11514_amd import _lib
+    import ctypes
+    L = _lib.lib()
+    out = (ctypes.c_double * 6)()
+    n = L.ct_probe_workspace_size()
+    assert n >= 4 * 256
+    assert L.ct_probe_alu_rates(None, ctypes.c_void_p(256), n, None) == _lib.CT_E_ARG
+    assert L.ct_probe_alu_rates(out, None, n, None) == _lib.CT_E_ARG
+    assert L.ct_probe_alu_rates(out, ctypes.c_void_p(256), n - 1, None) == _lib.CT_E_WORKSPACE
