@@ -97,6 +97,9 @@ def main() -> int:
                     help="also time the step captured into a HIP graph (replays)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer (reference kernel for HBM counters)")
+    ap.add_argument("--horizon-sweep", action="store_true",
+                    help="instead of the benchmark line: planner time versus horizon (the "
+                         "paper's timing benchmark shape), one JSON line per horizon")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -111,6 +114,9 @@ def main() -> int:
     from paper_2511_11514_amd import _lib
 
     dev = torch.device("cuda:0")
+    if args.horizon_sweep:
+        horizon_sweep(ct, torch, dev)
+        return 0
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -274,6 +280,53 @@ def main() -> int:
         res["cpu_baseline"] = cpu_baseline(x_np, y_np, w_np, g_np, eps, args.cpu_iters)
     print(json.dumps(res))
     return 0
+
+
+def horizon_sweep(ct, torch, dev) -> None:
+    """Planner wall time against the horizon T: the Stein flow with differential
+    drive and the Sinkhorn flow with the 3-D point mass (stand-in for the paper's
+    aircraft), each for its sweep's outer iterations on the GPU (flow on the GPU,
+    LQR on the host, ct_plan), beside one outer iteration of the FP64 oracle planner
+    on the host cores (bounded: Stein up to T = 5000)."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    cpu_limit = {"svgd_drive": 5000, "sinkhorn_aircraft": 2500}
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    for name, c in W.HORIZON_SWEEPS.items():
+        warm = True
+        for T in c["horizons"]:
+            s0, u0, y, w, g = W.horizon_inputs(name, T)
+            d = c["d"]
+            Q, R = c["Q"] * np.eye(d), c["R"] * np.eye(u0.shape[1])
+            if c["flow"] == "svgd":
+                kw = dict(gmm=ct.GMM.from_numpy(g, dev))
+                okw = dict(gmm=g)
+            else:
+                kw = dict(y=torch.as_tensor(y, device=dev), w=torch.as_tensor(w, device=dev),
+                          eps=c["eps"], iters=c["iters"])
+                okw = dict(y=y, w=w, eps=c["eps"], iters=c["iters"])
+            ct.plan(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"], 1, c["step"], **kw)  # warm-up
+            t0 = time.perf_counter()
+            _u, _s, hist = ct.plan(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"], c["outer"],
+                                   c["step"], **kw)
+            gpu = time.perf_counter() - t0
+            row = {"sweep": name, "flow": c["flow"], "dynamics": c["dynamics"], "d": d, "T": T,
+                   "M": None if y is None else len(y), "outer": c["outer"], "gpu_s": gpu,
+                   "gpu_s_per_outer": gpu / c["outer"], "first_objective": float(hist[0]),
+                   "last_objective": float(hist[-1])}
+            if T <= cpu_limit[name]:
+                if warm:  # the oracle's first call builds and loads its C library
+                    oracle.plan_step(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"],
+                                     step=c["step"], **okw)
+                    warm = False
+                t0 = time.perf_counter()
+                oracle.plan_step(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"], step=c["step"],
+                                 **okw)
+                cpu = time.perf_counter() - t0
+                row.update({"cpu_oracle_s_per_outer": cpu, "cpu_threads": threads,
+                            "oracle_over_gpu": cpu / (gpu / c["outer"])})
+            print(json.dumps(row), flush=True)
 
 
 def batched_leg(ct, torch, dev) -> dict:

@@ -321,7 +321,7 @@ __device__ __forceinline__ int upper_prefix(const int* pre, int n, int r) {
 
 template <int D, int R, int WS>
 __global__ __launch_bounds__(kBlock) void k_bpersist(BArgs A) {
-    __shared__ SweepSmem<D, R, WS> sm;
+    __shared__ SweepSmem<D, R> sm;
     __shared__ int s_unit;
     const BLayout& L = A.L;
     const BHeader H = *L.hdr;

@@ -9,7 +9,7 @@ namespace ct {
 
 template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP>
 __global__ __launch_bounds__(kBlock) void k_sweep(Launch L) {
-    __shared__ SweepSmem<D, R, WS> sm;
+    __shared__ SweepSmem<D, R> sm;
     const int bid = (int)blockIdx.x;
     int j = 0;
     while (j + 1 < L.njobs && bid >= L.blk_end[j]) ++j;
@@ -27,7 +27,6 @@ template <int D, bool LAGGED, bool BARY>
 __global__ __launch_bounds__(kBlock) void k_merge(Launch L, int R, int WS) {
     __shared__ int flist[kBlock];
     __shared__ int nflag;
-    __shared__ float red[kBlock * (2 + D)];
     const int bid = (int)blockIdx.x;
     int j = 0, start = 0;
     for (;;) {
@@ -42,8 +41,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(Launch L, int R, int WS) {
     __syncthreads();
     const int nqpad = J.nqb * 64 * R * (4 / WS);
     const int q = (bid - start) * kBlock + (int)threadIdx.x;
-    merge_rows<D, LAGGED, BARY>(J, q, nqpad, L.kappa, L.inv_kappa, L.inv_sqrt_kappa, flist, &nflag,
-                                red);
+    merge_rows<D, LAGGED, BARY>(J, q, nqpad, L.kappa, L.inv_kappa, L.inv_sqrt_kappa, flist, &nflag);
 }
 
 int plan_job(Job& j, const Schedule& s) {

@@ -208,11 +208,11 @@ __device__ __forceinline__ void finish_row(const Job& J, int q, float m, float s
 }
 
 // Recompute the flagged rows with a tracked maximum over every key of the job,
-// the whole block cooperating on one row at a time.  `red` is block-shared
-// scratch of kBlock * (2 + D) floats that no thread is still reading.
+// the whole block cooperating on one row at a time.
 template <int D, bool BARY>
-__device__ void rescue_rows(const Job& J, const int* flist, int nflag, float* red, float kappa,
+__device__ void rescue_rows(const Job& J, const int* flist, int nflag, float kappa,
                             float inv_kappa, float inv_sqrt_kappa) {
+    __shared__ float red[kBlock * (2 + D)];
     for (int f = 0; f < nflag; ++f) {
         const int q = flist[f];
         const float4 qc = J.qrec[q];
@@ -269,19 +269,11 @@ __device__ void rescue_rows(const Job& J, const int* flist, int nflag, float* re
     }
 }
 
-// Shared memory of one sweep work unit, sized to what the unit indexes: the
-// partials of the WS - 1 key-splitting waves that hand their rows to wave 0, or
-// (sep = 0 merge, row recomputation) kBlock * (2 + D) floats of scratch; and one
-// flag slot per query row of the block.  At most 13 KB for the 2-D schedules
-// with WS = 4, so LDS does not limit the blocks resident per CU.
-template <int D, int R, int WS>
+// Shared memory of one sweep work unit.
+template <int D, int R>
 struct SweepSmem {
-    static constexpr int kNC = 2 + D;
-    static constexpr int kQB = (4 / WS) * 64 * R;                     // query rows per block
-    static constexpr int kCombine = (WS - 1) * (4 / WS) * R * 64 * kNC;
-    static constexpr int kScratch = kBlock * kNC;
-    float part[kCombine > kScratch ? kCombine : kScratch];
-    int flist[kQB];                    // rows flagged for recomputation
+    float part[kBlock * R * (2 + D)];  // wave-split partials / merge scratch
+    int flist[kBlock * R];             // rows flagged for recomputation
     int nflag;
     int last;
 };
@@ -306,7 +298,7 @@ __device__ __forceinline__ void finish_or_flag(const Job& J, int q, float m, flo
 template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP = false>
 __device__ __forceinline__ void sweep_unit(const Job& J, int qb, int split, float kappa,
                                            float inv_kappa, float inv_sqrt_kappa,
-                                           SweepSmem<D, R, WS>& sm) {
+                                           SweepSmem<D, R>& sm) {
     constexpr int QW = 4 / WS;
     constexpr int NC = 2 + D;                  // components of a partial
     constexpr int QB = QW * 64 * R;            // queries per block
@@ -437,8 +429,7 @@ __device__ __forceinline__ void sweep_unit(const Job& J, int qb, int split, floa
     if (LAGGED) {
         __syncthreads();
         const int nflag = sm.nflag;
-        if (nflag > 0)
-            rescue_rows<D, BARY>(J, sm.flist, nflag, sm.part, kappa, inv_kappa, inv_sqrt_kappa);
+        if (nflag > 0) rescue_rows<D, BARY>(J, sm.flist, nflag, kappa, inv_kappa, inv_sqrt_kappa);
     }
 }
 
@@ -448,7 +439,7 @@ __device__ __forceinline__ void sweep_unit(const Job& J, int qb, int split, floa
 template <int D, bool LAGGED, bool BARY>
 __device__ __forceinline__ void merge_rows(const Job& J, int q, int nqpad, float kappa,
                                            float inv_kappa, float inv_sqrt_kappa, int* flist,
-                                           int* nflag, float* red) {
+                                           int* nflag) {
     const size_t cstride = (size_t)J.splits * nqpad;
     if (q < J.nq) {
         float m = LAGGED ? -J.qpot[q] * kappa : -FLT_MAX;
@@ -466,7 +457,7 @@ __device__ __forceinline__ void merge_rows(const Job& J, int q, int nqpad, float
     if (LAGGED) {
         __syncthreads();
         const int n = *nflag;
-        if (n > 0) rescue_rows<D, BARY>(J, flist, n, red, kappa, inv_kappa, inv_sqrt_kappa);
+        if (n > 0) rescue_rows<D, BARY>(J, flist, n, kappa, inv_kappa, inv_sqrt_kappa);
     }
 }
 

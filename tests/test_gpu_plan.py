@@ -69,3 +69,35 @@ def test_svgd_unicycle_plan_one_step_parity(ct):
                                                  step=0.5, gmm=g)
     assert abs(hist[0] - r_obj) / abs(r_obj) < 1e-5
     assert rel(u1 - u0, r_u1 - u0) < 1e-5
+
+
+@pytest.mark.parametrize("name,T", [("sinkhorn_aircraft", 300), ("svgd_drive", 500)])
+def test_horizon_sweep_workloads_one_step_parity(ct, name, T):
+    """The horizon-sweep workloads (Stein flow with differential drive; Sinkhorn
+    flow with the 3-D double integrator standing in for the aircraft): one outer
+    step from identical controls matches the oracle's, and the GPU planner keeps
+    decreasing its objective over the sweep's outer iterations."""
+    c = W.HORIZON_SWEEPS[name]
+    s0, u0, y, w, g = W.horizon_inputs(name, T)
+    d = c["d"]
+    Q, R = c["Q"] * np.eye(d), c["R"] * np.eye(u0.shape[1])
+    dev = torch.device("cuda")
+    kw = dict(gmm=ct.GMM.from_numpy(g, dev)) if c["flow"] == "svgd" else dict(
+        y=torch.as_tensor(y, device=dev), w=torch.as_tensor(w, device=dev), eps=c["eps"],
+        iters=c["iters"])
+    okw = dict(gmm=g) if c["flow"] == "svgd" else dict(y=y, w=w, eps=c["eps"], iters=c["iters"])
+    u1, _s, hist = ct.plan(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"], 1, c["step"], **kw)
+    r_u1, _rs, r_obj, _ra, _rv = oracle.plan_step(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"],
+                                                 step=c["step"], **okw)
+    assert abs(hist[0] - r_obj) / abs(r_obj) < 1e-5
+    assert rel(u1 - u0, r_u1 - u0) < 1e-5
+    _u, s, hist = ct.plan(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"], c["outer"],
+                          c["step"], **kw)
+    if c["flow"] == "sinkhorn":
+        assert np.all(np.diff(hist) < 0), hist
+    else:
+        # the Stein flow has no objective of its own: the samples' mean log-density
+        # under the target mixture must rise
+        s_init = oracle.rollout(c["dynamics"], s0, u0, c["dt"])
+        lp = lambda st: oracle.gmm_logpdf(st[1:, :d], g.weights, g.means, g.sigmas, g.floor).mean()
+        assert lp(s) > lp(s_init) + 5.0, (lp(s_init), lp(s))

@@ -26,6 +26,7 @@ import numpy as np
 __all__ = [
     "GMM", "gmm_params", "gmm_sample", "random_walk", "uniform_points",
     "positive_weights", "Config", "CONFIGS", "config_inputs", "batch_inputs",
+    "HORIZON_SWEEPS", "horizon_inputs",
 ]
 
 
@@ -144,6 +145,47 @@ CONFIGS = {
                           floor=0.1, extra=dict(dynamics="unicycle", dt=0.01, outer=20,
                                                 s0=(0.5, 0.5, 0.0), v0=0.3, omega_std=0.5)),
 }
+
+
+# Planner time-versus-horizon sweeps (the shape of the paper's timing benchmark,
+# Sec. III-A): the Stein flow with differential-drive (unicycle) dynamics over
+# horizons 100..1000 step 100 and 2000..10000 step 1000, and the Sinkhorn flow
+# over 100..500 step 100 and 1000..2500 step 500.  The paper's 3-D aircraft model
+# is not given; a 3-D double integrator (point mass with acceleration control)
+# stands in for it.  The Sinkhorn reference has as many samples as the horizon.
+# Control steps: 0.5 (Sinkhorn) and 0.05 (Stein: its flow scales with the mixture
+# score, ~1/sigma^2; steps of 0.1 and above diverge at some horizons of the sweep,
+# 0.05 raised the samples' mean log-density at every horizon tried, 100..2000).
+HORIZON_SWEEPS = {
+    "svgd_drive": dict(flow="svgd", dynamics="unicycle", d=2,
+                       horizons=list(range(100, 1001, 100)) + list(range(2000, 10001, 1000)),
+                       K_gmm=4, sigma=(0.05, 0.12), floor=0.0, dt=0.01, s0=(0.5, 0.5, 0.0),
+                       v0=0.3, omega_std=0.5, Q=1.0, R=0.01, step=0.05, outer=10, seed=6000),
+    "sinkhorn_aircraft": dict(flow="sinkhorn", dynamics="double_integrator", d=3,
+                              horizons=list(range(100, 501, 100)) + list(range(1000, 2501, 500)),
+                              K_gmm=4, sigma=(0.05, 0.12), floor=0.0, dt=0.05,
+                              s0=(0.5, 0.5, 0.5, 0.0, 0.0, 0.0), u_std=0.1, Q=1.0, R=0.01,
+                              step=0.5, outer=10, eps=0.01, iters=100, seed=7000),
+}
+
+
+def horizon_inputs(name: str, T: int):
+    """(s0 [n], u0 [T,m], y [M,d] or None, w [M] or None, gmm) for one horizon of a
+    sweep; seeded per (sweep, T)."""
+    c = HORIZON_SWEEPS[name]
+    d = c["d"]
+    rng = np.random.default_rng(c["seed"] + T)
+    g = gmm_params(rng, c["K_gmm"], d, c["sigma"][0], c["sigma"][1], False, c["floor"])
+    s0 = np.array(c["s0"], dtype=np.float64)
+    if c["dynamics"] == "unicycle":
+        u0 = np.stack([np.full(T, c["v0"]), rng.normal(size=T) * c["omega_std"]], axis=1)
+    else:
+        u0 = rng.normal(size=(T, d)) * c["u_std"]
+    y = w = None
+    if c["flow"] == "sinkhorn":
+        y = gmm_sample(rng, g, T)
+        w = np.ones(T, dtype=np.float32)
+    return s0, u0, y, w, g
 
 
 def config_inputs(cfg: Config, T: Optional[int] = None, M: Optional[int] = None):
