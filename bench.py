@@ -100,6 +100,9 @@ def main() -> int:
     ap.add_argument("--horizon-sweep", action="store_true",
                     help="instead of the benchmark line: planner time versus horizon (the "
                          "paper's timing benchmark shape), one JSON line per horizon")
+    ap.add_argument("--ensemble", action="store_true",
+                    help="instead of the benchmark line: a 16-seed planner ensemble in lockstep "
+                         "(one batched flow launch per outer iteration) against 16 plain runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,6 +119,9 @@ def main() -> int:
     dev = torch.device("cuda:0")
     if args.horizon_sweep:
         horizon_sweep(ct, torch, dev)
+        return 0
+    if args.ensemble:
+        ensemble_leg(ct, torch, dev)
         return 0
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -327,6 +333,36 @@ def horizon_sweep(ct, torch, dev) -> None:
                 row.update({"cpu_oracle_s_per_outer": cpu, "cpu_threads": threads,
                             "oracle_over_gpu": cpu / (gpu / c["outer"])})
             print(json.dumps(row), flush=True)
+
+
+def ensemble_leg(ct, torch, dev, S: int = 16, T: int = 1000) -> None:
+    """Seed ensemble of the Sinkhorn planner (3-D point-mass workload of the horizon
+    sweep, T = M = 1000, 10 outer iterations): ct_plan_ensemble against S
+    sequential ct_plan runs from the same seeds."""
+    import numpy as np
+    import workloads as W
+    c = W.HORIZON_SWEEPS["sinkhorn_aircraft"]
+    s0, _u0, y, w, _g = W.horizon_inputs("sinkhorn_aircraft", T)
+    rng = np.random.default_rng(321)
+    U0 = rng.normal(size=(S, T, c["d"])) * c["u_std"] * rng.uniform(0.5, 3.0, size=(S, 1, 1))
+    Q, R = c["Q"] * np.eye(c["d"]), c["R"] * np.eye(c["d"])
+    yt, wt = torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev)
+    kw = dict(y=yt, w=wt, eps=c["eps"], iters=c["iters"])
+    ct.plan_ensemble(c["dynamics"], s0, U0[:2], c["dt"], Q, R, 1, c["step"], **kw)  # warm-up
+    ct.plan(c["dynamics"], s0, U0[0], c["dt"], Q, R, "sinkhorn", 1, c["step"], **kw)
+    t0 = time.perf_counter()
+    _U, _s, values, best = ct.plan_ensemble(c["dynamics"], s0, U0, c["dt"], Q, R, c["outer"],
+                                            c["step"], **kw)
+    t_ens = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for b in range(S):
+        ct.plan(c["dynamics"], s0, U0[b], c["dt"], Q, R, "sinkhorn", c["outer"], c["step"], **kw)
+    t_seq = time.perf_counter() - t0
+    print(json.dumps({"ensemble": "sinkhorn_aircraft", "seeds": S, "T": T, "M": T,
+                      "outer": c["outer"], "ensemble_s": t_ens, "sequential_s": t_seq,
+                      "speedup": t_seq / t_ens, "best": best, "best_value": float(values[best]),
+                      "worst_value": float(values.max()),
+                      "median_value": float(np.median(values))}), flush=True)
 
 
 def batched_leg(ct, torch, dev) -> dict:

@@ -16,7 +16,9 @@
  *   ct_lqr_track              linear-quadratic flow matching (Sec. II-C, eqs. 8-10),
  *                             a sequential FP64 host solve;
  *   ct_plan                   the outer planning loop (Sec. II-A eqs. 2-3 with
- *                             Sec. II-C): flow on the GPU, LQR on the host.
+ *                             Sec. II-C): flow on the GPU, LQR on the host;
+ *   ct_plan_ensemble          many seeds of that loop in lockstep, their flows
+ *                             in one batched launch, the best seed reported.
  *
  * Conventions for every entry point
  * ---------------------------------
@@ -74,6 +76,8 @@ const char* ct_version(void);
                              run on a library-owned auxiliary stream of the current device, forked
                              from and joined back into `stream` with events, so they overlap the
                              cross sweeps; the fork/join is graph-capture compatible) */
+#define CT_PERSISTENT 128u /* batched path only: one persistent launch walking a dependency-
+                            ordered work list instead of lockstep launches per iteration */
 
 typedef struct ct_sinkhorn_opts {
     int32_t d;      /* 2 or 3 */
@@ -132,14 +136,17 @@ ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const floa
 
 /*
  * Many independent problems b = 0..B-1 of uneven size (the batched form of
- * ct_sinkhorn_grad, same definitions and options for every problem), evaluated
- * by one persistent kernel that walks a dependency-ordered work list.
+ * ct_sinkhorn_grad, same definitions and options for every problem).  Default:
+ * lockstep launches, two per iteration (every problem's f and self updates, then
+ * every problem's g update) over job tables prepared in the workspace, each job
+ * split over keys so that all blocks sweep about the same number of pairs.  With
+ * CT_PERSISTENT: one persistent kernel that walks a dependency-ordered work list.
  *   T_off, M_off  host [B+1]  prefix offsets: problem b owns x rows
  *                             T_off[b]..T_off[b+1]-1 and y rows M_off[b]..M_off[b+1]-1
  *                             (every problem needs T_b >= 1, M_b >= 1)
  *   x, y, w, grad_x, grad_w   concatenations in that order (w may be NULL)
  *   value         device [B] or NULL (requires CT_VALUE)
- * Flags: CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_SAFE_LSE (others: CT_E_ARG).
+ * Flags: CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_SAFE_LSE, CT_PERSISTENT (others: CT_E_ARG).
  * The workspace must first be prepared for this batch (same B, offsets, d, iters,
  * flags) by ct_sinkhorn_batched_prepare, which builds the work list on the host
  * and copies it into `ws`; ct_sinkhorn_grad_batched itself only enqueues kernels
@@ -261,6 +268,36 @@ size_t ct_plan_workspace_size(const ct_plan_problem* p, const ct_plan_opts* o, i
 ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, const float* y, const float* w,
                   int64_t M, const ct_gmm* q, double* u, double* s, double* hist, void* ws,
                   size_t ws_bytes, void* stream);
+
+/*
+ * Seed ensemble.  Different initial controls reach different, equally good
+ * optima of the planning problem (Sec. IV discussion), which several seeds can
+ * exploit for robustness.  ct_plan_ensemble runs S planners that share the
+ * problem p (dynamics, s0, T, dt), the options o and the reference samples, but
+ * start from their own controls, in lockstep: every outer iteration rolls out
+ * all seeds on the host, evaluates their S Sinkhorn flows in one persistent
+ * launch (ct_sinkhorn_grad_batched, gradient only) and solves the S LQR problems
+ * on the host, exactly as S independent ct_plan calls would.  After the last
+ * iteration the divergence of every final trajectory to the reference is
+ * evaluated in one more batched launch, and the seed with the smallest is
+ * reported.
+ *   S      seeds, >= 1 (S*T and S*M at most 2^30)
+ *   y, w   device [M][d], [M] or NULL: the shared reference (as in ct_plan)
+ *   u      host [S][T][m]  in: initial controls of every seed; out: final controls
+ *   s      host [S][T+1][n] or NULL  out: final state trajectories
+ *   value  host [S]  out: S(final trajectory of seed b, reference)
+ *   best   host [1]  out: index of the smallest value (lowest index on ties)
+ * Sinkhorn flow only (CT_E_UNSUPPORTED for the Stein flow, which has no
+ * objective to rank seeds by).  Synchronous.  The workspace holds every seed's
+ * samples, gradients and a copy of the reference per seed:
+ * ct_plan_ensemble_workspace_size(p, o, S, M, w != NULL) bytes.  Errors as
+ * ct_plan, plus CT_E_HIP if a batched evaluation returns a non-finite value.
+ */
+size_t ct_plan_ensemble_workspace_size(const ct_plan_problem* p, const ct_plan_opts* o, int32_t S,
+                                       int64_t M, int32_t weighted);
+ct_status ct_plan_ensemble(const ct_plan_problem* p, const ct_plan_opts* o, int32_t S,
+                           const float* y, const float* w, int64_t M, double* u, double* s,
+                           double* value, int32_t* best, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------- */
 /* Autotuning of the sweep kernels' tile and split schedule                    */

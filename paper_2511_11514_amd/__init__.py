@@ -8,7 +8,8 @@ from ._lib import (CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_WARM_START, CT_REF_CACHED,
                    CT_SAFE_LSE, CT_DYN_DOUBLE_INTEGRATOR, CT_DYN_UNICYCLE, CT_FLOW_SINKHORN,
                    CT_FLOW_SVGD, CtError, SinkhornOpts, GMMDesc, lib)
 from .api import (sinkhorn_grad, sinkhorn_grad_batched, SinkhornDivergence, BatchedSinkhorn,  # noqa: F401
-                  sinkhorn_divergence, svgd_grad, lqr_track, plan, autotune_sinkhorn,
+                  sinkhorn_divergence, svgd_grad, lqr_track, plan, plan_ensemble,
+                  autotune_sinkhorn,
                   tuning_table, tuning_save, tuning_load, tuning_clear, GMM, version,
                   probe_alu_rates)
 

@@ -26,6 +26,7 @@ CT_WARM_START = 8
 CT_REF_CACHED = 16
 CT_SAFE_LSE = 32
 CT_ONE_STREAM = 64
+CT_PERSISTENT = 128
 
 CT_DYN_DOUBLE_INTEGRATOR = 0
 CT_DYN_UNICYCLE = 1
@@ -82,6 +83,10 @@ _SIGS = {
     "ct_plan_workspace_size": (c_size_t, [POINTER(PlanProblem), POINTER(PlanOpts), c_int64]),
     "ct_plan": (c_int32, [POINTER(PlanProblem), POINTER(PlanOpts), P, P, c_int64, POINTER(GMMDesc),
                           PD, PD, PD, P, c_size_t, P]),
+    "ct_plan_ensemble_workspace_size": (c_size_t, [POINTER(PlanProblem), POINTER(PlanOpts),
+                                                   c_int32, c_int64, c_int32]),
+    "ct_plan_ensemble": (c_int32, [POINTER(PlanProblem), POINTER(PlanOpts), c_int32, P, P, c_int64,
+                                   PD, PD, PD, POINTER(c_int32), P, c_size_t, P]),
     "ct_autotune_sinkhorn": (c_int32, [c_int64, c_int64, POINTER(SinkhornOpts), P, c_size_t, P]),
     "ct_tuning_count": (c_int32, []),
     "ct_tuning_entry": (c_int32, [c_int32, POINTER(c_int32)]),

@@ -148,8 +148,9 @@ class BatchedOut:
 def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor],
                           ws: Optional[Sequence[torch.Tensor]] = None, *, eps: float, iters: int,
                           debias: bool = True, value: bool = False, grad_w: bool = False,
-                          safe: bool = False) -> BatchedOut:
-    """Many independent problems (ragged T_b, M_b) in one persistent launch."""
+                          safe: bool = False, persistent: bool = False) -> BatchedOut:
+    """Many independent problems (ragged T_b, M_b): lockstep launches over all of
+    them (default) or one persistent launch (persistent=True)."""
     B = len(xs)
     if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
         raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
@@ -164,7 +165,8 @@ def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor]
     y = _req(torch.cat([_req(t, "y", dev) for t in ys]), "y")
     w = None if ws is None else _req(torch.cat([_req(t, "w", dev) for t in ws]), "w")
     flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
-        (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0)
+        (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
+        (L.CT_PERSISTENT if persistent else 0)
     o = _opts(d, eps, iters, flags)
     to = T_off.ctypes.data_as(L.PI64)
     mo = M_off.ctypes.data_as(L.PI64)
@@ -189,7 +191,8 @@ class BatchedSinkhorn:
     it can be captured into a graph (capture()) and replayed."""
 
     def __init__(self, xs, ys, ws=None, *, eps: float, iters: int, debias: bool = True,
-                 value: bool = False, grad_w: bool = False, safe: bool = False):
+                 value: bool = False, grad_w: bool = False, safe: bool = False,
+                 persistent: bool = False):
         B = len(xs)
         if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
             raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
@@ -205,7 +208,8 @@ class BatchedSinkhorn:
         self.y = _req(torch.cat([_req(t, "y", self.dev) for t in ys]), "y")
         self.w = None if ws is None else _req(torch.cat([_req(t, "w", self.dev) for t in ws]), "w")
         flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
-            (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0)
+            (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
+            (L.CT_PERSISTENT if persistent else 0)
         self.o = _opts(self.d, eps, iters, flags)
         self._to = self.T_off.ctypes.data_as(L.PI64)
         self._mo = self.M_off.ctypes.data_as(L.PI64)
@@ -336,6 +340,39 @@ def plan(dynamics: str, s0, u, dt: float, Q, R, flow: str, outer: int, step: flo
                        _p(ws), nbytes, _stream(dev))
     check("ct_plan", st)
     return u, s, hist
+
+
+def plan_ensemble(dynamics: str, s0, U, dt: float, Q, R, outer: int, step: float = 1.0, *,
+                  y: torch.Tensor, w: Optional[torch.Tensor] = None, eps: float = 0.01,
+                  iters: int = 100, debias: bool = True):
+    """Seed ensemble of the Sinkhorn planner (ct_plan_ensemble): U [S,T,m] initial
+    controls.  Returns (U [S,T,m], s [S,T+1,n], values [S], best)."""
+    s0 = _f64(s0)
+    U = np.ascontiguousarray(_f64(U)).copy()
+    Q = _f64(Q)
+    R = _f64(R)
+    S, T, m = U.shape
+    d = Q.shape[0]
+    n = s0.shape[0]
+    dev = y.device
+    y = _req(y, "y", dev)
+    M = y.shape[0]
+    if w is not None:
+        w = _req(w, "w", dev)
+    prob = L.PlanProblem(_DYN[dynamics], d, T, float(dt), _dp(s0))
+    sk = _opts(d, eps, iters, L.CT_DEBIAS if debias else 0)
+    opts = L.PlanOpts(_FLOW["sinkhorn"], int(outer), float(step), _dp(Q), _dp(R), sk, 0.0)
+    s = np.empty((S, T + 1, n))
+    values = np.empty(S)
+    best = ctypes.c_int32(-1)
+    nbytes = lib().ct_plan_ensemble_workspace_size(ctypes.byref(prob), ctypes.byref(opts), S, M,
+                                                   1 if w is not None else 0)
+    ws = _workspace(nbytes, dev)
+    st = lib().ct_plan_ensemble(ctypes.byref(prob), ctypes.byref(opts), S, _p(y), _p(w), M,
+                                _dp(U), _dp(s), _dp(values), ctypes.byref(best), _p(ws), nbytes,
+                                _stream(dev))
+    check("ct_plan_ensemble", st)
+    return U, s, values, int(best.value)
 
 
 def autotune_sinkhorn(T: int, M: int, d: int, eps: float, device="cuda") -> None:

@@ -1,6 +1,14 @@
 // ct_sinkhorn_grad_batched: many independent Sinkhorn-divergence gradients of
-// uneven size (the per-problem definitions of sinkhorn.hip) in one persistent
-// launch.
+// uneven size (the per-problem definitions of sinkhorn.hip).
+//
+// Two executions of the same schedule of updates:
+//  * lockstep (default): per iteration two launches over job tables prepared in
+//    the workspace, A = every problem's f update and self updates, B = every
+//    problem's g update, then the extrapolation launches F1 and F2; each job is
+//    split over keys so that all blocks of a launch sweep about the same number
+//    of pairs (lockstep.hip), split jobs merged by a second kernel;
+//  * persistent (CT_PERSISTENT): one launch walking a dependency-ordered work
+//    list, described next.
 //
 // Work list.  Every problem runs the same stage sequence
 //     A_0, B_0, A_1, B_1, ..., A_{K-1}, B_{K-1}, F1, F2
@@ -57,6 +65,16 @@ struct BHeader {
     unsigned long long signature;
 };
 
+// Lockstep job tables: kinds A (self ping-pong cur = 0), A (cur = 1), B, F1, F2,
+// each with room for three jobs per problem.
+constexpr int kLockKinds = 5;
+struct LockInfo {
+    int njobs[kLockKinds], nblocks[kLockKinds], nmerge[kLockKinds];
+};
+// Lockstep schedule: four queries per lane, keys split over the four waves of a
+// block; about eight blocks per CU of equal work per launch.
+constexpr Schedule kLockSchedule{4, 4, 8, 1};
+
 // Device-side view of the prepared workspace.
 struct BLayout {
     BHeader* hdr;
@@ -68,6 +86,10 @@ struct BLayout {
     int* preF2;
     int* xoff;              // [B+1] padded x record offsets (for staging lookups)
     int* yoff;
+    Job* ljobs;             // [kLockKinds][3B] lockstep job tables
+    int* lblk;              // [kLockKinds][3B] sweep-block prefix ends
+    int* lmrg;              // [kLockKinds][3B] merge-block prefix ends
+    float* lpart;           // partial sums of split lockstep jobs (one launch at a time)
     unsigned* done;         // [B] completed units per problem
     unsigned* head;         // [1] next unit
     unsigned* counters;     // [4]
@@ -83,7 +105,7 @@ struct BLayout {
 };
 
 static BLayout b_layout(void* ws, int B, int64_t sumT, int64_t sumM, int64_t sumTpad,
-                        int64_t sumMpad, int d) {
+                        int64_t sumMpad, int d, size_t part_floats) {
     Arena a(ws);
     BLayout L;
     L.hdr = a.take<BHeader>(1);
@@ -95,7 +117,11 @@ static BLayout b_layout(void* ws, int B, int64_t sumT, int64_t sumM, int64_t sum
     L.preF2 = a.take<int>(B + 1);
     L.xoff = a.take<int>(B + 1);
     L.yoff = a.take<int>(B + 1);
+    L.ljobs = a.take<Job>((size_t)kLockKinds * 3 * B);
+    L.lblk = a.take<int>((size_t)kLockKinds * 3 * B);
+    L.lmrg = a.take<int>((size_t)kLockKinds * 3 * B);
     L.table_bytes = a.off;
+    L.lpart = a.take<float>(part_floats);
     L.done = a.take<unsigned>(B);
     L.head = a.take<unsigned>(1);
     L.counters = a.take<unsigned>(4);
@@ -453,7 +479,11 @@ __global__ __launch_bounds__(256) void k_breduce(BLayout L, float kappa, float* 
 namespace {
 
 std::mutex g_prep_mu;
-std::map<const void*, unsigned long long> g_prepared;   // workspace -> signature
+struct Prepared {
+    unsigned long long signature;
+    LockInfo lock;
+};
+std::map<const void*, Prepared> g_prepared;   // workspace -> what it was prepared for
 
 unsigned long long signature(int B, const int64_t* To, const int64_t* Mo, const ct_sinkhorn_opts* o,
                              const Schedule& sc) {
@@ -486,7 +516,7 @@ ct_status b_validate(int B, const int64_t* To, const int64_t* Mo, const ct_sinkh
     if (o->d != 2 && o->d != 3) return fail(CT_E_SHAPE, "d must be 2 or 3");
     if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(CT_E_ARG, "eps must be finite and > 0");
     if (o->iters < 0) return fail(CT_E_ARG, "iters must be >= 0");
-    if (o->flags & ~(uint32_t)(CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_SAFE_LSE))
+    if (o->flags & ~(uint32_t)(CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_SAFE_LSE | CT_PERSISTENT))
         return fail(CT_E_ARG, "unsupported flags for the batched path");
     if (To[0] != 0 || Mo[0] != 0) return fail(CT_E_SHAPE, "offsets must start at 0");
     S = BatchSizes{0, 0, 0, 0};
@@ -511,6 +541,140 @@ Schedule batched_schedule(int d) {
     return Schedule{2, 4, 0, 0};
 }
 
+// Sizes and record offsets of every problem (the part of BProb the lockstep
+// tables need).
+std::vector<BProb> base_probs(int B, const int64_t* To, const int64_t* Mo) {
+    std::vector<BProb> P(B);
+    int xp = 0, yp = 0;
+    for (int b = 0; b < B; ++b) {
+        std::memset(&P[b], 0, sizeof(BProb));
+        P[b].T = (int)(To[b + 1] - To[b]);
+        P[b].M = (int)(Mo[b + 1] - Mo[b]);
+        P[b].xo = (int)To[b];
+        P[b].yo = (int)Mo[b];
+        P[b].xp = xp;
+        P[b].yp = yp;
+        P[b].Tpad = pad_keys(P[b].T);
+        P[b].Mpad = pad_keys(P[b].M);
+        P[b].log2a = (float)(-std::log2((double)P[b].T));
+        xp += P[b].Tpad;
+        yp += P[b].Mpad;
+    }
+    return P;
+}
+
+// The job of kind 0 f, 1 p, 2 q, 3 g (fin: extrapolation pass) of problem P,
+// with pointers into the device layout L (the host mirror of unit_job, full
+// query ranges).
+Job lock_job(const BLayout& L, const BProb& P, int kind, int cur, bool fin, int d) {
+    Job J;
+    std::memset(&J, 0, sizeof(Job));
+    J.rescued = L.counters + 1;
+    J.qlog2w_s = P.log2a;
+    if (kind == 0) {
+        J.qrec = L.cx + P.xo; J.qpot = L.f + P.xo;
+        J.krec = L.yrec[0] + P.yp; J.nq = P.T; J.nk = P.M;
+        J.out_pot = (fin ? L.fp : L.f) + P.xo;
+        J.out_rec = (fin ? L.xrec[1] : L.xrec[0]) + P.xp;
+        if (fin) J.out_bary = L.dy + (size_t)P.xo * d;
+    } else if (kind == 1) {
+        J.qrec = L.cx + P.xo; J.qpot = L.p + P.xo;
+        J.krec = L.xrec[2 + cur] + P.xp; J.nq = P.T; J.nk = P.T;
+        if (fin) {
+            J.out_pot = L.pp + P.xo;
+            J.out_bary = L.ds + (size_t)P.xo * d;
+        } else {
+            J.self_avg = 1;
+            J.out_pot = L.p + P.xo;
+            J.out_rec = L.xrec[2 + (cur ^ 1)] + P.xp;
+        }
+    } else if (kind == 2) {
+        J.qrec = L.cy + P.yo; J.qpot = L.q + P.yo; J.qlog2w = L.log2b + P.yo;
+        J.krec = L.yrec[1 + cur] + P.yp; J.nq = P.M; J.nk = P.M;
+        if (fin) {
+            J.out_pot = L.qp + P.yo;
+        } else {
+            J.self_avg = 1;
+            J.out_pot = L.q + P.yo;
+            J.out_rec = L.yrec[1 + (cur ^ 1)] + P.yp;
+        }
+    } else {
+        J.qrec = L.cy + P.yo; J.qpot = L.g + P.yo; J.qlog2w = L.log2b + P.yo;
+        J.krec = (fin ? L.xrec[1] : L.xrec[0]) + P.xp; J.nq = P.M; J.nk = P.T;
+        J.out_pot = (fin ? L.gp : L.g) + P.yo;
+        J.out_rec = fin ? nullptr : L.yrec[0] + P.yp;
+    }
+    return J;
+}
+
+// Build the five lockstep job tables (jobs, sweep-block and merge-block prefix
+// ends) into the given arrays ([kLockKinds][3B] each) and their sizes; returns
+// the floats of partial sums the largest launch needs.
+size_t build_lock(const BLayout& L, const std::vector<BProb>& P, uint32_t flags, int K, int d,
+                  Job* jobs, int* blk, int* mrg, LockInfo& info) {
+    const int B = (int)P.size();
+    const bool debias = flags & CT_DEBIAS;
+    const bool want_v = flags & (CT_VALUE | CT_GRAD_W);
+    const bool need_ref = debias && want_v;
+    const Schedule sc = kLockSchedule;
+    const int qpb = 64 * sc.R * (4 / sc.WS);
+    const int curF = K & 1;
+    size_t part_max = 0;
+    for (int k = 0; k < kLockKinds; ++k) {
+        std::vector<Job> js;
+        for (int b = 0; b < B; ++b) {
+            if (k <= 1) {
+                js.push_back(lock_job(L, P[b], 0, k, false, d));
+                if (debias) js.push_back(lock_job(L, P[b], 1, k, false, d));
+                if (need_ref) js.push_back(lock_job(L, P[b], 2, k, false, d));
+            } else if (k == 2) {
+                js.push_back(lock_job(L, P[b], 3, 0, false, d));
+            } else if (k == 3) {
+                js.push_back(lock_job(L, P[b], 0, curF, true, d));
+                if (debias) js.push_back(lock_job(L, P[b], 1, curF, true, d));
+            } else if (want_v) {
+                js.push_back(lock_job(L, P[b], 3, curF, true, d));
+                if (need_ref) js.push_back(lock_job(L, P[b], 2, curF, true, d));
+            }
+        }
+        double pairs = 0.0;
+        for (const Job& j : js) pairs += (double)j.nq * pad_keys(j.nk);
+        const double ppb = pairs / ((double)kNumCU * sc.blocks_per_cu);
+        int nb = 0, nm = 0;
+        size_t part = 0;
+        Job* jt = jobs + (size_t)k * 3 * B;
+        for (size_t i = 0; i < js.size(); ++i) {
+            Job& j = js[i];
+            nb += plan_job_target(j, sc, ppb);
+            if (j.splits > 1) {
+                j.part = L.lpart + part;
+                part += (size_t)(2 + d) * j.splits * (size_t)j.nqb * qpb;
+                nm += (j.nq + kBlock - 1) / kBlock;
+            }
+            jt[i] = j;
+            blk[(size_t)k * 3 * B + i] = nb;
+            mrg[(size_t)k * 3 * B + i] = nm;
+        }
+        info.njobs[k] = (int)js.size();
+        info.nblocks[k] = nb;
+        info.nmerge[k] = nm;
+        part_max = std::max(part_max, part);
+    }
+    return part_max;
+}
+
+// Floats of lockstep partial sums for this batch (the planning does not depend
+// on where the workspace is).
+size_t lock_part_floats(int B, const int64_t* To, const int64_t* Mo, const ct_sinkhorn_opts* o,
+                        const BatchSizes& S) {
+    const std::vector<BProb> P = base_probs(B, To, Mo);
+    const BLayout L0 = b_layout(nullptr, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d, 0);
+    std::vector<Job> jobs((size_t)kLockKinds * 3 * B);
+    std::vector<int> blk(jobs.size()), mrg(jobs.size());
+    LockInfo info;
+    return build_lock(L0, P, o->flags, o->iters, o->d, jobs.data(), blk.data(), mrg.data(), info);
+}
+
 }  // namespace
 
 }  // namespace ct
@@ -521,7 +685,8 @@ extern "C" size_t ct_sinkhorn_batched_workspace_size(int32_t B, const int64_t* T
                                                      const ct_sinkhorn_opts* o) {
     BatchSizes S;
     if (b_validate(B, To, Mo, o, S)) return 0;
-    return b_layout(nullptr, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d).bytes;
+    const size_t pf = lock_part_floats(B, To, Mo, o, S);
+    return b_layout(nullptr, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d, pf).bytes;
 }
 
 extern "C" ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* To, const int64_t* Mo,
@@ -533,7 +698,8 @@ extern "C" ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* To, c
     if (rc) return rc;
     if (!ws) return fail(CT_E_ARG, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
-    BLayout L = b_layout(ws, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d);
+    const size_t pf = lock_part_floats(B, To, Mo, o, S);
+    BLayout L = b_layout(ws, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d, pf);
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
     const Schedule sc = batched_schedule(o->d);
     const int QB = 64 * sc.R * (4 / sc.WS);
@@ -544,7 +710,7 @@ extern "C" ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* To, c
 
     // host image of the table: header, problems, order, prefixes, record offsets
     std::vector<char> img(L.table_bytes, 0);
-    BLayout H0 = b_layout(img.data(), B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d);
+    BLayout H0 = b_layout(img.data(), B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d, pf);
     BHeader& H = *H0.hdr;
     std::vector<double> cost(B);
     int xp = 0, yp = 0;
@@ -611,11 +777,15 @@ extern "C" ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* To, c
     H.sumTpad = (int)S.sumTpad;
     H.sumMpad = (int)S.sumMpad;
     H.signature = signature(B, To, Mo, o, sc);
+    // lockstep tables: device pointers of the real workspace, written into the image
+    LockInfo info;
+    const std::vector<BProb> BP = base_probs(B, To, Mo);
+    build_lock(L, BP, o->flags, o->iters, o->d, H0.ljobs, H0.lblk, H0.lmrg, info);
     hipStream_t st = static_cast<hipStream_t>(stream);
     CT_CHECK_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
     CT_CHECK_HIP(hipStreamSynchronize(st));
     std::lock_guard<std::mutex> lk(g_prep_mu);
-    g_prepared[ws] = H.signature;
+    g_prepared[ws] = Prepared{H.signature, info};
     return CT_OK;
 }
 
@@ -634,15 +804,18 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
     if (value && !(o->flags & CT_VALUE)) return fail(CT_E_ARG, "value given without CT_VALUE");
     if (!value && (o->flags & CT_VALUE)) return fail(CT_E_ARG, "CT_VALUE needs value");
     if (!ws) return fail(CT_E_ARG, "workspace is null");
-    BLayout L = b_layout(ws, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d);
+    const size_t pf = lock_part_floats(B, To, Mo, o, S);
+    BLayout L = b_layout(ws, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d, pf);
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
     const Schedule sc = batched_schedule(o->d);
+    LockInfo info;
     {
         std::lock_guard<std::mutex> lk(g_prep_mu);
         auto it = g_prepared.find(ws);
-        if (it == g_prepared.end() || it->second != signature(B, To, Mo, o, sc))
+        if (it == g_prepared.end() || it->second.signature != signature(B, To, Mo, o, sc))
             return fail(CT_E_ARG, "workspace not prepared for this batch "
                                   "(call ct_sinkhorn_batched_prepare first)");
+        info = it->second.lock;
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double kappa_d = kLog2e / (double)o->eps;
@@ -652,6 +825,45 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
     hipLaunchKernelGGL(k_bstage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, L, x, y, w,
                        (float)std::sqrt(kappa_d), (float)kappa_d);
     CT_CHECK_HIP(hipGetLastError());
+    if (!(o->flags & CT_PERSISTENT)) {
+        // lockstep: two launches per iteration, then the extrapolation launches
+        TabLaunch T0;
+        std::memset(&T0, 0, sizeof(T0));
+        T0.kappa = (float)kappa_d;
+        T0.inv_kappa = (float)(1.0 / kappa_d);
+        T0.inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
+        auto run_kind = [&](int k, bool lagged, bool bary) -> ct_status {
+            if (info.njobs[k] == 0) return CT_OK;
+            TabLaunch t = T0;
+            t.jobs = L.ljobs + (size_t)k * 3 * B;
+            t.blk_end = L.lblk + (size_t)k * 3 * B;
+            t.mrg_end = L.lmrg + (size_t)k * 3 * B;
+            t.njobs = info.njobs[k];
+            t.nblocks = info.nblocks[k];
+            t.nmerge = info.nmerge[k];
+            CT_CHECK_HIP(launch_tab(o->d, kLockSchedule, lagged, bary, t, st));
+            return CT_OK;
+        };
+        const bool safe_only = o->flags & CT_SAFE_LSE;
+        void* tok = profile_begin(st);
+        for (int k = 0; k < o->iters; ++k) {
+            const bool lagged = !safe_only && k > 0;
+            rc = run_kind(k & 1, lagged, false);
+            if (rc) return rc;
+            rc = run_kind(2, lagged, false);
+            if (rc) return rc;
+        }
+        const bool lagged_final = !safe_only && o->iters > 0;
+        rc = run_kind(3, lagged_final, true);
+        if (rc) return rc;
+        rc = run_kind(4, lagged_final, false);
+        if (rc) return rc;
+        if (tok) profile_end(tok, st, 4, 0, kLockSchedule.R * 100 + kLockSchedule.WS * 10, 0, 0.0);
+        hipLaunchKernelGGL(k_breduce, dim3(B), dim3(256), 0, st, L, (float)kappa_d, grad_x, grad_w,
+                           value);
+        CT_CHECK_HIP(hipGetLastError());
+        return CT_OK;
+    }
     BArgs A;
     A.L = L;
     A.kappa = (float)kappa_d;

@@ -101,6 +101,23 @@ int schedule_candidates(Schedule* out, int max);
 hipError_t launch_sweep(int d, const Schedule& sc, bool lagged, bool bary, const Launch& L,
                         int nblocks, hipStream_t s);
 
+// Lockstep launches over a job table in device memory (the batched path): job j
+// owns sweep blocks [blk_end[j-1], blk_end[j]) and merge blocks
+// [mrg_end[j-1], mrg_end[j]) (none when it has a single key split).
+struct TabLaunch {
+    const Job* jobs;
+    const int* blk_end;
+    const int* mrg_end;
+    int njobs;
+    int nblocks, nmerge;
+    float kappa, inv_kappa, inv_sqrt_kappa;
+};
+// Plan nqb/splits/kps of `j` so that one block sweeps about `pairs_per_block` pairs.
+int plan_job_target(Job& j, const Schedule& s, double pairs_per_block);
+// Sweep kernel (separate-merge mode) then, if any job is split, the merge kernel.
+hipError_t launch_tab(int d, const Schedule& sc, bool lagged, bool bary, const TabLaunch& L,
+                      hipStream_t s);
+
 // Per-launch event timing (ct_profile_enable); no-ops when disabled.
 bool profiling();
 void* profile_begin(hipStream_t s);

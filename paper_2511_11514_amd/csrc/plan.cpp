@@ -1,5 +1,6 @@
 // Host side of the planner (Sec. II-C): the FP64 tracking LQR of eqs. 9-10 and
 // the outer loop that alternates GPU flow evaluation with the LQR step.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -373,5 +374,173 @@ extern "C" ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, co
         for (size_t i = 0; i < v.size(); ++i) u[i] += o->step * v[i];
     }
     if (s) rollout(p->dynamics, D, p->s0, u, T, p->dt, s);
+    return CT_OK;
+}
+
+// ------------------------------------------------------------ seed ensemble
+
+namespace ct {
+namespace {
+
+struct EnsembleLayout {
+    float* x;       // [S*T][d] trajectory samples of every seed
+    float* gx;      // [S*T][d] gradients
+    float* y;       // [S*M][d] the reference, once per seed
+    float* w;       // [S*M] its weights, or null
+    float* value;   // [S]
+    void* inner;    // batched Sinkhorn workspace
+    size_t inner_bytes;
+    size_t bytes;
+};
+
+void ensemble_offsets(int32_t S, int64_t T, int64_t M, std::vector<int64_t>& To,
+                      std::vector<int64_t>& Mo) {
+    To.resize((size_t)S + 1);
+    Mo.resize((size_t)S + 1);
+    for (int32_t b = 0; b <= S; ++b) {
+        To[b] = (int64_t)b * T;
+        Mo[b] = (int64_t)b * M;
+    }
+}
+
+EnsembleLayout ensemble_layout(void* ws, const ct_plan_problem* p, const ct_plan_opts* o,
+                               int32_t S, int64_t M, bool weighted) {
+    Arena a(ws);
+    EnsembleLayout L;
+    const int64_t T = p->T;
+    const int d = p->d;
+    L.x = a.take<float>((size_t)S * T * d);
+    L.gx = a.take<float>((size_t)S * T * d);
+    L.y = a.take<float>((size_t)S * M * d);
+    L.w = weighted ? a.take<float>((size_t)S * M) : nullptr;
+    L.value = a.take<float>((size_t)S);
+    std::vector<int64_t> To, Mo;
+    ensemble_offsets(S, T, M, To, Mo);
+    ct_sinkhorn_opts so = o->sk;
+    so.d = d;
+    so.flags &= (uint32_t)(CT_DEBIAS | CT_SAFE_LSE);
+    const size_t b0 = ct_sinkhorn_batched_workspace_size(S, To.data(), Mo.data(), &so);
+    so.flags |= CT_VALUE;
+    const size_t b1 = ct_sinkhorn_batched_workspace_size(S, To.data(), Mo.data(), &so);
+    L.inner_bytes = std::max(b0, b1);
+    L.inner = a.take<char>(L.inner_bytes);
+    L.bytes = a.off + 256;
+    return L;
+}
+
+}  // namespace
+}  // namespace ct
+
+extern "C" size_t ct_plan_ensemble_workspace_size(const ct_plan_problem* p, const ct_plan_opts* o,
+                                                  int32_t S, int64_t M, int32_t weighted) {
+    Dyn D;
+    if (!p || !o || !dyn_dims(p, D) || p->T < 1 || S < 1 || M < 1) return 0;
+    return ensemble_layout(nullptr, p, o, S, M, weighted != 0).bytes;
+}
+
+extern "C" ct_status ct_plan_ensemble(const ct_plan_problem* p, const ct_plan_opts* o, int32_t S,
+                                      const float* y, const float* w, int64_t M, double* u,
+                                      double* s, double* value, int32_t* best, void* ws,
+                                      size_t ws_bytes, void* stream) {
+    clear_error();
+    Dyn D;
+    ct_status rc = plan_validate(p, o, y, M, nullptr, D);
+    if (rc) return rc;
+    if (o->flow != CT_FLOW_SINKHORN)
+        return fail(CT_E_UNSUPPORTED, "the seed ensemble ranks seeds by the Sinkhorn divergence; "
+                                      "it needs the Sinkhorn flow");
+    if (S < 1) return fail(CT_E_ARG, "S must be >= 1");
+    if (!u || !value || !best) return fail(CT_E_ARG, "u, value and best must be non-null");
+    if (!ws) return fail(CT_E_ARG, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
+    const int64_t T = p->T;
+    if ((int64_t)S * T > (int64_t(1) << 30) || (int64_t)S * M > (int64_t(1) << 30))
+        return fail(CT_E_SHAPE, "S*T and S*M must be <= 2^30");
+    EnsembleLayout L = ensemble_layout(ws, p, o, S, M, w != nullptr);
+    if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int d = D.d, n = D.n, m = D.m;
+    std::vector<int64_t> To, Mo;
+    ensemble_offsets(S, T, M, To, Mo);
+    // the shared reference, once per seed (the batched form takes one reference per problem)
+    for (int32_t b = 0; b < S; ++b) {
+        CT_CHECK_HIP(hipMemcpyAsync(L.y + (size_t)b * M * d, y, sizeof(float) * M * d,
+                                    hipMemcpyDeviceToDevice, st));
+        if (w)
+            CT_CHECK_HIP(hipMemcpyAsync(L.w + (size_t)b * M, w, sizeof(float) * M,
+                                        hipMemcpyDeviceToDevice, st));
+    }
+    ct_sinkhorn_opts so = o->sk;
+    so.d = d;
+    so.flags &= (uint32_t)(CT_DEBIAS | CT_SAFE_LSE);
+    rc = ct_sinkhorn_batched_prepare(S, To.data(), Mo.data(), &so, L.inner, L.inner_bytes, stream);
+    if (rc) return rc;
+    std::vector<double> traj((size_t)(T + 1) * n), A((size_t)T * n * n), B((size_t)T * n * m);
+    std::vector<double> tgt((size_t)T * n, 0.0), v((size_t)T * m), Qn((size_t)n * n, 0.0);
+    std::vector<float> xh((size_t)S * T * d), gh((size_t)S * T * d);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) Qn[i * n + j] = o->Q[i * d + j];
+    auto stage_positions = [&]() -> ct_status {
+        for (int32_t b = 0; b < S; ++b) {
+            rollout(p->dynamics, D, p->s0, u + (size_t)b * T * m, T, p->dt, traj.data());
+            for (int64_t t = 0; t < T; ++t)
+                for (int k = 0; k < d; ++k)
+                    xh[((size_t)b * T + t) * d + k] = (float)traj[(t + 1) * n + k];
+        }
+        CT_CHECK_HIP(hipMemcpyAsync(L.x, xh.data(), sizeof(float) * S * T * d,
+                                    hipMemcpyHostToDevice, st));
+        return CT_OK;
+    };
+    for (int it = 0; it < o->outer; ++it) {
+        rc = stage_positions();
+        if (rc) return rc;
+        // every seed's flow in one persistent launch (the gradient only: the
+        // reference self term is not needed for it)
+        rc = ct_sinkhorn_grad_batched(S, To.data(), Mo.data(), L.x, L.y, L.w, &so, L.gx, nullptr,
+                                      nullptr, L.inner, L.inner_bytes, stream);
+        if (rc) return rc;
+        CT_CHECK_HIP(hipMemcpyAsync(gh.data(), L.gx, sizeof(float) * S * T * d,
+                                    hipMemcpyDeviceToHost, st));
+        CT_CHECK_HIP(hipStreamSynchronize(st));
+        for (int32_t b = 0; b < S; ++b) {
+            double* ub = u + (size_t)b * T * m;
+            rollout(p->dynamics, D, p->s0, ub, T, p->dt, traj.data());
+            for (int64_t t = 0; t < T; ++t)
+                for (int k = 0; k < d; ++k)
+                    tgt[t * n + k] = -(double)T * (double)gh[((size_t)b * T + t) * d + k];
+            for (int64_t t = 0; t < T; ++t)
+                dyn_jac(p->dynamics, D, traj.data() + t * n, ub + t * m,
+                        A.data() + (size_t)t * n * n, B.data() + (size_t)t * n * m);
+            rc = lqr_solve(T, n, m, p->dt, A.data(), B.data(), tgt.data(), Qn.data(), o->R,
+                           v.data(), nullptr);
+            if (rc) return rc;
+            for (size_t i = 0; i < v.size(); ++i) ub[i] += o->step * v[i];
+        }
+    }
+    // rank the final trajectories by their divergence to the reference
+    rc = stage_positions();
+    if (rc) return rc;
+    ct_sinkhorn_opts sv = so;
+    sv.flags |= CT_VALUE;
+    rc = ct_sinkhorn_batched_prepare(S, To.data(), Mo.data(), &sv, L.inner, L.inner_bytes, stream);
+    if (rc) return rc;
+    rc = ct_sinkhorn_grad_batched(S, To.data(), Mo.data(), L.x, L.y, L.w, &sv, L.gx, nullptr,
+                                  L.value, L.inner, L.inner_bytes, stream);
+    if (rc) return rc;
+    std::vector<float> vh((size_t)S);
+    CT_CHECK_HIP(hipMemcpyAsync(vh.data(), L.value, sizeof(float) * S, hipMemcpyDeviceToHost, st));
+    CT_CHECK_HIP(hipStreamSynchronize(st));
+    int32_t bi = 0;
+    for (int32_t b = 0; b < S; ++b) {
+        value[b] = vh[b];
+        if (!std::isfinite(vh[b]))
+            return fail(CT_E_HIP, "seed %d: the batched evaluation returned a non-finite value", b);
+        if (vh[b] < vh[bi]) bi = b;
+    }
+    *best = bi;
+    if (s)
+        for (int32_t b = 0; b < S; ++b)
+            rollout(p->dynamics, D, p->s0, u + (size_t)b * T * m, T, p->dt,
+                    s + (size_t)b * (T + 1) * n);
     return CT_OK;
 }

@@ -119,3 +119,30 @@ def test_probe_rejects_bad_arguments_before_launch():
     assert L.ct_probe_alu_rates(None, ctypes.c_void_p(256), n, None) == _lib.CT_E_ARG
     assert L.ct_probe_alu_rates(out, None, n, None) == _lib.CT_E_ARG
     assert L.ct_probe_alu_rates(out, ctypes.c_void_p(256), n - 1, None) == _lib.CT_E_WORKSPACE
+
+
+def test_plan_ensemble_rejects_bad_arguments_before_launch():
+    import numpy as np
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    s0 = np.zeros(6)
+    Q, R = np.eye(3), 0.01 * np.eye(3)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    prob = _lib.PlanProblem(_lib.CT_DYN_DOUBLE_INTEGRATOR, 3, 10, 0.05, dp(s0))
+    sk = _lib.SinkhornOpts(3, 10, 0.01, _lib.CT_DEBIAS)
+    u = np.zeros((2, 10, 3))
+    val = np.zeros(2)
+    best = ctypes.c_int32()
+    P = ctypes.c_void_p
+    def call(flow=_lib.CT_FLOW_SINKHORN, S=2, uu=u, ws=256):
+        o = _lib.PlanOpts(flow, 1, 0.5, dp(Q), dp(R), sk, 0.0)
+        return L.ct_plan_ensemble(ctypes.byref(prob), ctypes.byref(o), S, P(256), None, 20,
+                                  None if uu is None else dp(uu), None, dp(val), ctypes.byref(best),
+                                  P(ws), 1 << 30, None)
+    assert call(flow=_lib.CT_FLOW_SVGD) in (_lib.CT_E_ARG, _lib.CT_E_UNSUPPORTED)
+    assert call(S=0) == _lib.CT_E_ARG
+    assert call(uu=None) == _lib.CT_E_ARG
+    assert call(ws=0) == _lib.CT_E_ARG
+    o = _lib.PlanOpts(_lib.CT_FLOW_SINKHORN, 1, 0.5, dp(Q), dp(R), sk, 0.0)
+    assert L.ct_plan_ensemble_workspace_size(ctypes.byref(prob), ctypes.byref(o), 2, 20, 0) > 0
+    assert L.ct_plan_ensemble_workspace_size(ctypes.byref(prob), ctypes.byref(o), 0, 20, 0) == 0

@@ -1,5 +1,7 @@
-"""Batched persistent path (ct_sinkhorn_grad_batched) against the FP64 oracle
-per problem and against the per-problem path; graph capture and replay."""
+"""Batched path (ct_sinkhorn_grad_batched), in both executions — lockstep launches
+over job tables (default) and the persistent work-list kernel (CT_PERSISTENT) —
+against the FP64 oracle per problem and against the per-problem path; graph
+capture and replay."""
 import numpy as np
 import pytest
 
@@ -33,11 +35,15 @@ def _batch(ct, probs, eps, iters, **kw):
     return bs
 
 
+MODES = [pytest.param(False, id="lockstep"), pytest.param(True, id="persistent")]
+
+
+@pytest.mark.parametrize("persistent", MODES)
 @pytest.mark.parametrize("d", [2, 3])
-def test_ragged_batch_matches_oracle(ct, d):
+def test_ragged_batch_matches_oracle(ct, d, persistent):
     probs = _ragged(11 + d, 9, 700, 1500, d)
     eps, iters = 0.01, 25
-    bs = _batch(ct, probs, eps, iters)
+    bs = _batch(ct, probs, eps, iters, persistent=persistent)
     bs.run()
     torch.cuda.synchronize()
     gx = bs.split(bs.grad_x.cpu().numpy(), bs.T_off)
@@ -50,11 +56,12 @@ def test_ragged_batch_matches_oracle(ct, d):
         assert max(e) < TOL, (b, len(x), len(y), e)
 
 
-def test_batched_equals_plain_and_graph_replay(ct):
+@pytest.mark.parametrize("persistent", MODES)
+def test_batched_equals_plain_and_graph_replay(ct, persistent):
     probs = _ragged(21, 12, 900, 2000)
     eps, iters = 0.01, 30
     dev = torch.device("cuda")
-    bs = _batch(ct, probs, eps, iters)
+    bs = _batch(ct, probs, eps, iters, persistent=persistent)
     bs.run()
     torch.cuda.synchronize()
     ref_x = bs.grad_x.clone()
@@ -94,11 +101,12 @@ def test_unprepared_workspace_is_rejected(ct):
     assert st == _lib.CT_E_ARG
 
 
-def test_scaled_batch_workload_sampled(ct):
+@pytest.mark.parametrize("persistent", MODES)
+def test_scaled_batch_workload_sampled(ct, persistent):
     """The 256-problem batch shape at 1/8 of its sizes; four problems checked."""
     cfg = W.CONFIGS["batched_2d"]
     probs = W.batch_inputs(cfg, B=48, scale=0.125)
-    bs = _batch(ct, probs, cfg.eps, 40)
+    bs = _batch(ct, probs, cfg.eps, 40, persistent=persistent)
     bs.run()
     torch.cuda.synchronize()
     gx = bs.split(bs.grad_x.cpu().numpy(), bs.T_off)
@@ -107,3 +115,46 @@ def test_scaled_batch_workload_sampled(ct):
         x, y, w = probs[b]
         r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=40)
         assert rel(gx[b], r.grad_x) < TOL and abs(val[b] - r.value) < TOL * abs(r.value)
+
+
+def test_mode_mismatch_is_rejected(ct):
+    """A workspace prepared for lockstep launches is not valid for the persistent
+    kernel (the mode is part of what was prepared)."""
+    import ctypes
+    from paper_2511_11514_amd import _lib
+    probs = _ragged(41, 3, 50, 80)
+    bs = _batch(ct, probs, 0.05, 5)
+    o = _lib.SinkhornOpts(bs.o.d, bs.o.iters, bs.o.eps, bs.o.flags | _lib.CT_PERSISTENT)
+    P = ctypes.c_void_p
+    st = _lib.lib().ct_sinkhorn_grad_batched(bs.B, bs._to, bs._mo, P(bs.x.data_ptr()),
+                                             P(bs.y.data_ptr()), P(bs.w.data_ptr()), ctypes.byref(o),
+                                             P(bs.grad_x.data_ptr()), P(bs.grad_w.data_ptr()),
+                                             P(bs.value.data_ptr()), P(bs.ws.data_ptr()), bs.nbytes,
+                                             None)
+    assert st == _lib.CT_E_ARG
+
+
+@pytest.mark.parametrize("iters,debias,safe", [(0, True, False), (1, True, False), (6, False, False),
+                                               (6, True, True)])
+def test_lockstep_edge_cases(ct, iters, debias, safe):
+    """Lockstep launches: no iteration, one (cold) iteration, the non-debiased and
+    the tracked-maximum modes, on a batch with single-point and tiny problems."""
+    probs = _ragged(51, 7, 300, 600)
+    probs[0] = (probs[0][0][:1], probs[0][1][:1], probs[0][2][:1])
+    eps = 0.02
+    dev = torch.device("cuda")
+    t = lambda a: torch.as_tensor(a, device=dev)
+    bs = ct.BatchedSinkhorn([t(p[0]) for p in probs], [t(p[1]) for p in probs],
+                            [t(p[2]) for p in probs], eps=eps, iters=iters, debias=debias,
+                            value=True, grad_w=True, safe=safe)
+    bs.run()
+    torch.cuda.synchronize()
+    gx = bs.split(bs.grad_x.cpu().numpy(), bs.T_off)
+    gw = bs.split(bs.grad_w.cpu().numpy(), bs.M_off)
+    val = bs.value.cpu().numpy()
+    for b, (x, y, w) in enumerate(probs):
+        r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters, debias=debias)
+        scale = max(np.abs(r.grad_x).max(), 1e-30)
+        assert np.abs(gx[b] - r.grad_x).max() <= TOL * scale + 1e-7, b
+        assert rel(gw[b], r.grad_w) < TOL or np.abs(gw[b] - r.grad_w).max() < 1e-6, b
+        assert abs(val[b] - r.value) <= TOL * abs(r.value) + 1e-7, b

@@ -101,3 +101,55 @@ def test_horizon_sweep_workloads_one_step_parity(ct, name, T):
         s_init = oracle.rollout(c["dynamics"], s0, u0, c["dt"])
         lp = lambda st: oracle.gmm_logpdf(st[1:, :d], g.weights, g.means, g.sigmas, g.floor).mean()
         assert lp(s) > lp(s_init) + 5.0, (lp(s_init), lp(s))
+
+
+def _ensemble_inputs(S, T):
+    c = W.HORIZON_SWEEPS["sinkhorn_aircraft"]
+    s0, _u0, y, w, g = W.horizon_inputs("sinkhorn_aircraft", T)
+    rng = np.random.default_rng(123)
+    U0 = rng.normal(size=(S, T, c["d"])) * c["u_std"] * (1.0 + np.arange(S))[:, None, None]
+    Q, R = c["Q"] * np.eye(c["d"]), c["R"] * np.eye(c["d"])
+    return c, s0, U0, y, w, Q, R
+
+
+def test_plan_ensemble_matches_oracle_per_seed(ct):
+    """Seed ensemble (ct_plan_ensemble): one outer step of every seed matches the
+    oracle's step from that seed's controls, the reported values are the oracle's
+    divergence of each final trajectory, and the best seed is their argmin."""
+    S, T = 3, 200
+    c, s0, U0, y, w, Q, R = _ensemble_inputs(S, T)
+    dev = torch.device("cuda")
+    U1, s, values, best = ct.plan_ensemble(c["dynamics"], s0, U0, c["dt"], Q, R, 1, c["step"],
+                                           y=torch.as_tensor(y, device=dev),
+                                           w=torch.as_tensor(w, device=dev), eps=c["eps"],
+                                           iters=c["iters"])
+    ref_vals = []
+    for b in range(S):
+        r_u1, _rs, _obj, _a, _v = oracle.plan_step(c["dynamics"], s0, U0[b], c["dt"], Q, R,
+                                                  "sinkhorn", step=c["step"], y=y, w=w,
+                                                  eps=c["eps"], iters=c["iters"])
+        assert rel(U1[b] - U0[b], r_u1 - U0[b]) < 1e-5, b
+        np.testing.assert_allclose(s[b], oracle.rollout(c["dynamics"], s0, U1[b], c["dt"]),
+                                   rtol=1e-12, atol=1e-12)
+        xf = s[b][1:, :c["d"]].astype(np.float32).astype(np.float64)
+        ref_vals.append(oracle.sinkhorn(xf, y, w, eps=c["eps"], iters=c["iters"]).value)
+    ref_vals = np.array(ref_vals)
+    np.testing.assert_allclose(values, ref_vals, rtol=1e-5)
+    assert best == int(np.argmin(ref_vals))
+
+
+def test_plan_ensemble_equals_independent_plans(ct):
+    """The lockstep ensemble follows the same trajectories as S independent
+    planner runs (batched vs per-problem sweeps differ only in rounding)."""
+    S, T, outer = 4, 300, 5
+    c, s0, U0, y, w, Q, R = _ensemble_inputs(S, T)
+    dev = torch.device("cuda")
+    yt, wt = torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev)
+    U, s, values, best = ct.plan_ensemble(c["dynamics"], s0, U0, c["dt"], Q, R, outer, c["step"],
+                                          y=yt, w=wt, eps=c["eps"], iters=c["iters"])
+    for b in range(S):
+        ub, _sb, _h = ct.plan(c["dynamics"], s0, U0[b], c["dt"], Q, R, "sinkhorn", outer,
+                              c["step"], y=yt, w=wt, eps=c["eps"], iters=c["iters"])
+        assert rel(U[b] - U0[b], ub - U0[b]) < 1e-4, b
+    assert np.all(np.isfinite(values)) and 0 <= best < S
+    assert values[best] == values.min()
