@@ -70,10 +70,19 @@ struct BHeader {
 constexpr int kLockKinds = 5;
 struct LockInfo {
     int njobs[kLockKinds], nblocks[kLockKinds], nmerge[kLockKinds];
+    Schedule sc;            // the schedule the tables were planned for
 };
-// Lockstep schedule: four queries per lane, keys split over the four waves of a
-// block; about eight blocks per CU of equal work per launch.
+// Default lockstep schedule: four queries per lane, keys split over the four
+// waves of a block, about eight blocks per CU of equal work per launch; a tuned
+// entry under the (d, 1, 0) key of the tuning table replaces it.
 constexpr Schedule kLockSchedule{4, 4, 8, 1};
+
+static Schedule lock_schedule(int d) {
+    Schedule s;
+    if (tuning_lookup(d, 1, 0, s) && (s.R == 1 || s.R == 2 || s.R == 4) && (s.WS == 2 || s.WS == 4))
+        return Schedule{s.R, s.WS, s.blocks_per_cu, 1};
+    return kLockSchedule;
+}
 
 // Device-side view of the prepared workspace.
 struct BLayout {
@@ -501,6 +510,8 @@ unsigned long long signature(int B, const int64_t* To, const int64_t* Mo, const 
     mix((unsigned)o->iters);
     mix(o->flags);
     mix((unsigned)(sc.R * 16 + sc.WS));
+    const Schedule ls = lock_schedule(o->d);
+    mix((unsigned)(ls.R * 4096 + ls.WS * 256 + ls.blocks_per_cu));
     return h;
 }
 
@@ -611,12 +622,11 @@ Job lock_job(const BLayout& L, const BProb& P, int kind, int cur, bool fin, int 
 // ends) into the given arrays ([kLockKinds][3B] each) and their sizes; returns
 // the floats of partial sums the largest launch needs.
 size_t build_lock(const BLayout& L, const std::vector<BProb>& P, uint32_t flags, int K, int d,
-                  Job* jobs, int* blk, int* mrg, LockInfo& info) {
+                  const Schedule& sc, Job* jobs, int* blk, int* mrg, LockInfo& info) {
     const int B = (int)P.size();
     const bool debias = flags & CT_DEBIAS;
     const bool want_v = flags & (CT_VALUE | CT_GRAD_W);
     const bool need_ref = debias && want_v;
-    const Schedule sc = kLockSchedule;
     const int qpb = 64 * sc.R * (4 / sc.WS);
     const int curF = K & 1;
     size_t part_max = 0;
@@ -655,6 +665,7 @@ size_t build_lock(const BLayout& L, const std::vector<BProb>& P, uint32_t flags,
             blk[(size_t)k * 3 * B + i] = nb;
             mrg[(size_t)k * 3 * B + i] = nm;
         }
+        info.sc = sc;
         info.njobs[k] = (int)js.size();
         info.nblocks[k] = nb;
         info.nmerge[k] = nm;
@@ -672,7 +683,8 @@ size_t lock_part_floats(int B, const int64_t* To, const int64_t* Mo, const ct_si
     std::vector<Job> jobs((size_t)kLockKinds * 3 * B);
     std::vector<int> blk(jobs.size()), mrg(jobs.size());
     LockInfo info;
-    return build_lock(L0, P, o->flags, o->iters, o->d, jobs.data(), blk.data(), mrg.data(), info);
+    return build_lock(L0, P, o->flags, o->iters, o->d, lock_schedule(o->d), jobs.data(), blk.data(),
+                      mrg.data(), info);
 }
 
 }  // namespace
@@ -780,7 +792,8 @@ extern "C" ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* To, c
     // lockstep tables: device pointers of the real workspace, written into the image
     LockInfo info;
     const std::vector<BProb> BP = base_probs(B, To, Mo);
-    build_lock(L, BP, o->flags, o->iters, o->d, H0.ljobs, H0.lblk, H0.lmrg, info);
+    build_lock(L, BP, o->flags, o->iters, o->d, lock_schedule(o->d), H0.ljobs, H0.lblk, H0.lmrg,
+               info);
     hipStream_t st = static_cast<hipStream_t>(stream);
     CT_CHECK_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
     CT_CHECK_HIP(hipStreamSynchronize(st));
@@ -832,6 +845,7 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
         T0.kappa = (float)kappa_d;
         T0.inv_kappa = (float)(1.0 / kappa_d);
         T0.inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
+        const Schedule lsc = info.sc;
         auto run_kind = [&](int k, bool lagged, bool bary) -> ct_status {
             if (info.njobs[k] == 0) return CT_OK;
             TabLaunch t = T0;
@@ -841,7 +855,7 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
             t.njobs = info.njobs[k];
             t.nblocks = info.nblocks[k];
             t.nmerge = info.nmerge[k];
-            CT_CHECK_HIP(launch_tab(o->d, kLockSchedule, lagged, bary, t, st));
+            CT_CHECK_HIP(launch_tab(o->d, lsc, lagged, bary, t, st));
             return CT_OK;
         };
         const bool safe_only = o->flags & CT_SAFE_LSE;
@@ -858,7 +872,7 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
         if (rc) return rc;
         rc = run_kind(4, lagged_final, false);
         if (rc) return rc;
-        if (tok) profile_end(tok, st, 4, 0, kLockSchedule.R * 100 + kLockSchedule.WS * 10, 0, 0.0);
+        if (tok) profile_end(tok, st, 4, 0, lsc.R * 100 + lsc.WS * 10, 0, 0.0);
         hipLaunchKernelGGL(k_breduce, dim3(B), dim3(256), 0, st, L, (float)kappa_d, grad_x, grad_w,
                            value);
         CT_CHECK_HIP(hipGetLastError());
