@@ -13,6 +13,10 @@
  *                             size in one persistent launch;
  *   ct_svgd_grad              Stein variational flow (Sec. II-B, eq. 4) with an
  *                             RBF kernel and an analytic Gaussian-mixture score;
+ *   ct_svgd_grad_score        the same flow for any score in device memory;
+ *   ct_grid_score, ct_grid_samples  a reference given as a continuous utility on
+ *                             a grid (Sec. II-A): its score for the Stein flow,
+ *                             its weighted nodes for the Sinkhorn flow;
  *   ct_lqr_track              linear-quadratic flow matching (Sec. II-C, eqs. 8-10),
  *                             a sequential FP64 host solve;
  *   ct_plan                   the outer planning loop (Sec. II-A eqs. 2-3 with
@@ -30,7 +34,8 @@
  *   contents need not be initialised and are clobbered.
  * - GPU entry points are asynchronous on `stream` (a hipStream_t; NULL = the
  *   null stream): they enqueue kernels and return without synchronising, except
- *   ct_plan, which is synchronous.  Two calls that share a workspace must be
+ *   ct_sinkhorn_batched_prepare, ct_grid_samples, ct_plan and ct_plan_ensemble,
+ *   which are synchronous.  Two calls that share a workspace must be
  *   ordered on one stream.
  * - Arguments are validated on the host before anything is enqueued; an invalid
  *   call returns a negative status, enqueues nothing and leaves a message for
@@ -202,6 +207,72 @@ size_t ct_svgd_workspace_size(int64_t T, int32_t d);
 ct_status ct_svgd_grad(const float* x, int64_t T, int32_t d, const ct_gmm* q, float h, float* phi,
                        float* score, float* h_used, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * The Stein flow phi of ct_svgd_grad for a score the caller supplies (Sec. II-B:
+ * the flow uses the target only through grad log q, so q may be unnormalised).
+ *   score   device [T][d]  grad log q(x_i), read only
+ * Same workspace (ct_svgd_workspace_size), bandwidth rule, outputs and errors as
+ * ct_svgd_grad (CT_E_ARG for a null score instead of the mixture checks).  Given
+ * the score that ct_svgd_grad computes for a mixture, the result is identical.
+ */
+ct_status ct_svgd_grad_score(const float* x, int64_t T, int32_t d, const float* score, float h,
+                             float* phi, float* h_used, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Continuous-utility references on a grid (Sec. II-A)                        */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * A utility map: values u_j >= 0 on the nodes of a regular grid over the box
+ * [lo, hi] (n[t] >= 2 nodes on axis t; node index j_t at
+ * lo_t + j_t (hi_t - lo_t) / (n_t - 1)).  The reference density is proportional
+ * to U(x) + floor, with U the multilinear interpolant of the node values at x
+ * clamped into the box (constant along an axis outside it).  At most 2^20 nodes
+ * per axis and 2^28 in all.
+ */
+typedef struct ct_grid {
+    int32_t n[3];   /* nodes per axis (n[2] unused when d = 2) */
+    float lo[3];    /* box lower corner (finite) */
+    float hi[3];    /* box upper corner (finite, hi > lo) */
+    const float* u; /* device, node values, axis 0 fastest: u[j0 + n0 (j1 + n1 j2)] */
+    float floor;    /* additive floor >= 0, in the units of u */
+} ct_grid;
+
+/*
+ * score[i] = grad log(U + floor) at x_i, in float64 rounded to float32: the
+ * gradient of the multilinear piece of the cell holding x_i (a point on a face
+ * shared by two cells takes the upper cell, the last cell on the box's upper
+ * face); zero along an axis on which x_i lies outside the box; zero where
+ * U + floor = 0; NaN for a non-finite x_i.  Scaling u and floor by one constant
+ * leaves it unchanged.  Node values are not checked (negative ones give
+ * meaningless scores).  No workspace.
+ *   x      device [T][d]
+ *   g      host struct with a device array
+ *   score  device [T][d] out
+ * Errors: CT_E_ARG (null x/score/g/u, box not finite or hi <= lo, floor < 0 or not
+ * finite), CT_E_SHAPE (d not 2/3, T < 1 or > 2^30, node counts out of range).
+ */
+ct_status ct_grid_score(const float* x, int64_t T, int32_t d, const ct_grid* g, float* score,
+                        void* stream);
+
+/*
+ * The utility as weighted reference samples for the Sinkhorn flow: every node
+ * with weight (u_j + floor) times its trapezoid-rule volume (the cell volume,
+ * halved once for each axis on which the node lies on the box face; the rule is
+ * exact for the interpolant's mass), normalised to sum 1 in float64; nodes of
+ * zero weight are dropped; order is node order.  Synchronous (the count M is
+ * returned on the host).
+ *   y   device [N][d] out, N = n0 n1 (n2): the first M rows are written
+ *   w   device [N] out: the first M entries are written
+ *   M   host [1] out: number of samples
+ *   ws  workspace of ct_grid_samples_workspace_size(g, d) bytes
+ * Errors: as ct_grid_score, plus CT_E_ARG for null y/w/M/ws, a negative or
+ * non-finite node value, or a utility that is zero everywhere (with floor 0).
+ */
+size_t ct_grid_samples_workspace_size(const ct_grid* g, int32_t d);
+ct_status ct_grid_samples(const ct_grid* g, int32_t d, float* y, float* w, int64_t* M, void* ws,
+                          size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------- */
 /* Linear-quadratic flow matching (Sec. II-C, eqs. 8-10), host FP64            */
 /* ------------------------------------------------------------------------- */
@@ -231,6 +302,7 @@ ct_status ct_lqr_track(int64_t T, int32_t n, int32_t m, double dt, const double*
 #define CT_DYN_UNICYCLE 1          /* state (p_x, p_y, heading), control (speed, turn rate); d = 2 */
 #define CT_FLOW_SINKHORN 0
 #define CT_FLOW_SVGD 1
+#define CT_FLOW_SVGD_GRID 2        /* Stein flow toward a utility grid (opts.grid) */
 
 typedef struct ct_plan_problem {
     int32_t dynamics; /* CT_DYN_* */
@@ -248,6 +320,7 @@ typedef struct ct_plan_opts {
     const double* R;     /* host [m][m] */
     ct_sinkhorn_opts sk; /* Sinkhorn settings (flow = CT_FLOW_SINKHORN) */
     float svgd_h;        /* Stein bandwidth, <= 0 for the median heuristic */
+    const ct_grid* grid; /* Stein target for CT_FLOW_SVGD_GRID, else unused (may be NULL) */
 } ct_plan_opts;
 
 size_t ct_plan_workspace_size(const ct_plan_problem* p, const ct_plan_opts* o, int64_t M);
@@ -255,11 +328,14 @@ size_t ct_plan_workspace_size(const ct_plan_problem* p, const ct_plan_opts* o, i
 /*
  * Each outer iteration: roll the dynamics forward with Euler steps from s0 under
  * u; take the positions of s_1..s_T as the trajectory samples; evaluate the
- * reference flow on the GPU (Sinkhorn: -T dS/dx_i; Stein: phi_i); linearise the
- * dynamics along (s_t, u_t) (eq. 8); solve ct_lqr_track with the flow as the
- * target of the position block; update u <- u + step v*.  Synchronous.
+ * reference flow on the GPU (Sinkhorn: -T dS/dx_i; Stein: phi_i, with the
+ * mixture's score for CT_FLOW_SVGD or the utility grid's (ct_grid_score) for
+ * CT_FLOW_SVGD_GRID); linearise the dynamics along (s_t, u_t) (eq. 8); solve
+ * ct_lqr_track with the flow as the target of the position block; update
+ * u <- u + step v*.  Synchronous.  A utility map reaches the Sinkhorn flow as the
+ * samples of ct_grid_samples.
  *   y, w    device reference samples/weights (Sinkhorn flow; w may be NULL)
- *   q       host struct (Stein flow), else NULL
+ *   q       host struct (CT_FLOW_SVGD), else NULL
  *   u       host [T][m] controls, in/out
  *   s       host [T+1][n] out: final rollout (after the last update), or NULL
  *   hist    host [outer] out: S (Sinkhorn) or mean |phi_i| (Stein) at the start

@@ -13,12 +13,16 @@ Each function follows the paper's definitions directly, in float64:
 * ``gmm_score``, ``median_bandwidth``, ``svgd_phi`` - the Stein variational
                    flow with an RBF kernel and an analytic mixture score
                    (Sec. II-B, eq. 4);
+* ``grid``       - a reference given as a utility on a grid: its score for the
+                   Stein flow and its weighted nodes for the Sinkhorn flow
+                   (Sec. II-A, Sec. II-B);
 * ``lqr_track_dense``, ``lqr_track_riccati`` - linear-quadratic flow matching
                    (Sec. II-C, eqs. 8-10);
 * ``plan_step`` / ``plan`` - the outer planning loop (Sec. II-C).
 """
 from .sinkhorn import sinkhorn, lse_update, gauge_fix, SinkhornResult  # noqa: F401
 from .svgd import gmm_score, gmm_logpdf, median_bandwidth, svgd_phi, pair_count  # noqa: F401
+from . import grid  # noqa: F401
 from .lqr import lqr_track_dense, lqr_track_riccati  # noqa: F401
 from .plan import (dynamics_f, dynamics_jac, rollout, plan_step, plan,  # noqa: F401
                    reference_flow)

@@ -24,6 +24,7 @@ import numpy as np
 from .lqr import lqr_track_riccati
 from .sinkhorn import sinkhorn
 from .svgd import gmm_score, median_bandwidth, svgd_phi
+from .grid import score as grid_score
 
 
 def dynamics_f(kind: str, s: np.ndarray, u: np.ndarray) -> np.ndarray:
@@ -72,15 +73,22 @@ def rollout(kind: str, s0, u, dt: float) -> np.ndarray:
     return s
 
 
-def reference_flow(flow: str, x, y=None, w=None, gmm=None, eps=0.01, iters=100, h=None):
+def reference_flow(flow: str, x, y=None, w=None, gmm=None, eps=0.01, iters=100, h=None,
+                   grid=None):
     """(flow [T,d], scalar): the per-sample reference flow and the objective
-    reported for it (S for Sinkhorn, mean |phi| for Stein)."""
+    reported for it (S for Sinkhorn, mean |phi| for Stein; "svgd_grid" is the
+    Stein flow toward a utility grid, oracle.grid.Grid)."""
     T = x.shape[0]
     if flow == "sinkhorn":
         r = sinkhorn(x, y, w, eps=eps, iters=iters, want_value=True, want_grad_w=False)
         return -T * r.grad_x, r.value
     if flow == "svgd":
         sc = gmm_score(x, gmm.weights, gmm.means, gmm.sigmas, gmm.floor)
+        hh = median_bandwidth(x) if (h is None or h <= 0) else h
+        phi = svgd_phi(x, sc, hh)
+        return phi, float(np.mean(np.linalg.norm(phi, axis=1)))
+    if flow == "svgd_grid":
+        sc = grid_score(grid, x)
         hh = median_bandwidth(x) if (h is None or h <= 0) else h
         phi = svgd_phi(x, sc, hh)
         return phi, float(np.mean(np.linalg.norm(phi, axis=1)))

@@ -6,11 +6,12 @@ for device memory and streams.
 """
 from ._lib import (CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_WARM_START, CT_REF_CACHED,  # noqa: F401
                    CT_SAFE_LSE, CT_DYN_DOUBLE_INTEGRATOR, CT_DYN_UNICYCLE, CT_FLOW_SINKHORN,
-                   CT_FLOW_SVGD, CtError, SinkhornOpts, GMMDesc, lib)
+                   CT_FLOW_SVGD, CT_FLOW_SVGD_GRID, CtError, SinkhornOpts, GMMDesc, GridDesc,
+                   lib)
 from .api import (sinkhorn_grad, sinkhorn_grad_batched, SinkhornDivergence, BatchedSinkhorn,  # noqa: F401
                   sinkhorn_divergence, svgd_grad, lqr_track, plan, plan_ensemble,
                   autotune_sinkhorn,
                   tuning_table, tuning_save, tuning_load, tuning_clear, GMM, version,
-                  probe_alu_rates)
+                  probe_alu_rates, svgd_grad_score, UtilityGrid, grid_score, grid_samples)
 
 __version__ = "0.1.0"

@@ -32,6 +32,7 @@ CT_DYN_DOUBLE_INTEGRATOR = 0
 CT_DYN_UNICYCLE = 1
 CT_FLOW_SINKHORN = 0
 CT_FLOW_SVGD = 1
+CT_FLOW_SVGD_GRID = 2
 
 
 class SinkhornOpts(ctypes.Structure):
@@ -43,6 +44,11 @@ class GMMDesc(ctypes.Structure):
                 ("floor", c_float)]
 
 
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n", c_int32 * 3), ("lo", c_float * 3), ("hi", c_float * 3), ("u", c_void_p),
+                ("floor", c_float)]
+
+
 class PlanProblem(ctypes.Structure):
     _fields_ = [("dynamics", c_int32), ("d", c_int32), ("T", c_int64), ("dt", c_double),
                 ("s0", POINTER(c_double))]
@@ -50,7 +56,8 @@ class PlanProblem(ctypes.Structure):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("flow", c_int32), ("outer", c_int32), ("step", c_double), ("Q", POINTER(c_double)),
-                ("R", POINTER(c_double)), ("sk", SinkhornOpts), ("svgd_h", c_float)]
+                ("R", POINTER(c_double)), ("sk", SinkhornOpts), ("svgd_h", c_float),
+                ("grid", POINTER(GridDesc))]
 
 
 class CtError(RuntimeError):
@@ -79,6 +86,10 @@ _SIGS = {
     "ct_svgd_workspace_size": (c_size_t, [c_int64, c_int32]),
     "ct_svgd_grad": (c_int32, [P, c_int64, c_int32, POINTER(GMMDesc), c_float, P, P, P, P,
                                c_size_t, P]),
+    "ct_svgd_grad_score": (c_int32, [P, c_int64, c_int32, P, c_float, P, P, P, c_size_t, P]),
+    "ct_grid_score": (c_int32, [P, c_int64, c_int32, POINTER(GridDesc), P, P]),
+    "ct_grid_samples_workspace_size": (c_size_t, [POINTER(GridDesc), c_int32]),
+    "ct_grid_samples": (c_int32, [POINTER(GridDesc), c_int32, P, P, PI64, P, c_size_t, P]),
     "ct_lqr_track": (c_int32, [c_int64, c_int32, c_int32, c_double, PD, PD, PD, PD, PD, PD, PD]),
     "ct_plan_workspace_size": (c_size_t, [POINTER(PlanProblem), POINTER(PlanOpts), c_int64]),
     "ct_plan": (c_int32, [POINTER(PlanProblem), POINTER(PlanOpts), P, P, c_int64, POINTER(GMMDesc),

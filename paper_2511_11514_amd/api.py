@@ -280,6 +280,85 @@ def svgd_grad(x: torch.Tensor, gmm: GMM, h: Optional[float] = None, *, return_sc
     return (phi, hu, score) if return_score else (phi, hu)
 
 
+def svgd_grad_score(x: torch.Tensor, score: torch.Tensor, h: Optional[float] = None):
+    """Stein variational flow phi (eq. 4) for a score already on the GPU (any
+    unnormalised target).  Returns (phi, h_used)."""
+    dev = x.device
+    x = _req(x, "x")
+    score = _req(score, "score", dev)
+    T, d = x.shape
+    if tuple(score.shape) != (T, d):
+        raise ValueError(f"score must have shape {(T, d)}, got {tuple(score.shape)}")
+    phi = torch.empty_like(x)
+    hu = torch.empty(1, dtype=torch.float32, device=dev)
+    nbytes = lib().ct_svgd_workspace_size(T, d)
+    ws = _workspace(nbytes, dev)
+    st = lib().ct_svgd_grad_score(_p(x), T, d, _p(score), float(h if h else 0.0), _p(phi), _p(hu),
+                                  _p(ws), nbytes, _stream(dev))
+    check("ct_svgd_grad_score", st)
+    return phi, hu
+
+
+@dataclass
+class UtilityGrid:
+    """Utility map on a regular grid over the box [lo, hi] (a continuous-utility
+    reference): u [n1, n0] (d = 2) or [n2, n1, n0] (d = 3) on the GPU, axis 0
+    varying fastest; the density is proportional to its multilinear interpolant
+    plus ``floor``."""
+    u: torch.Tensor
+    lo: Sequence[float]
+    hi: Sequence[float]
+    floor: float = 0.0
+
+    @property
+    def d(self) -> int:
+        return self.u.dim()
+
+    def desc(self) -> L.GridDesc:
+        d = self.d
+        if d not in (2, 3):
+            raise ValueError("u must have 2 or 3 dimensions")
+        if len(self.lo) != d or len(self.hi) != d:
+            raise ValueError("lo and hi need one entry per axis")
+        self.u = _req(self.u, "u")
+        n = list(reversed(self.u.shape)) + [1] * (3 - d)
+        pad = lambda v: [float(a) for a in v] + [0.0] * (3 - d)
+        return L.GridDesc((ctypes.c_int32 * 3)(*n), (ctypes.c_float * 3)(*pad(self.lo)),
+                          (ctypes.c_float * 3)(*pad(self.hi)), self.u.data_ptr(), float(self.floor))
+
+
+def grid_score(x: torch.Tensor, grid: UtilityGrid) -> torch.Tensor:
+    """grad log(U + floor) at every sample (the utility grid's score)."""
+    x = _req(x, "x", grid.u.device)
+    T, d = x.shape
+    if d != grid.d:
+        raise ValueError(f"x has d={d}, the grid d={grid.d}")
+    desc = grid.desc()
+    score = torch.empty_like(x)
+    st = lib().ct_grid_score(_p(x), T, d, ctypes.byref(desc), _p(score), _stream(x.device))
+    check("ct_grid_score", st)
+    return score
+
+
+def grid_samples(grid: UtilityGrid):
+    """The utility's nodes as weighted reference samples for the Sinkhorn flow:
+    (y [M,d], w [M]), trapezoid-rule weights normalised to 1, zero-weight nodes
+    dropped.  Synchronous."""
+    desc = grid.desc()
+    d = grid.d
+    dev = grid.u.device
+    N = grid.u.numel()
+    y = torch.empty((N, d), dtype=torch.float32, device=dev)
+    w = torch.empty(N, dtype=torch.float32, device=dev)
+    M = ctypes.c_int64(0)
+    nbytes = lib().ct_grid_samples_workspace_size(ctypes.byref(desc), d)
+    ws = _workspace(nbytes, dev)
+    st = lib().ct_grid_samples(ctypes.byref(desc), d, _p(y), _p(w), ctypes.byref(M), _p(ws), nbytes,
+                               _stream(dev))
+    check("ct_grid_samples", st)
+    return y[:M.value], w[:M.value]
+
+
 def _dp(a: np.ndarray):
     return a.ctypes.data_as(L.PD)
 
@@ -300,14 +379,15 @@ def lqr_track(A, B, a, Q, R, dt: float):
 
 
 _DYN = {"double_integrator": L.CT_DYN_DOUBLE_INTEGRATOR, "unicycle": L.CT_DYN_UNICYCLE}
-_FLOW = {"sinkhorn": L.CT_FLOW_SINKHORN, "svgd": L.CT_FLOW_SVGD}
+_FLOW = {"sinkhorn": L.CT_FLOW_SINKHORN, "svgd": L.CT_FLOW_SVGD, "svgd_grid": L.CT_FLOW_SVGD_GRID}
 
 
 def plan(dynamics: str, s0, u, dt: float, Q, R, flow: str, outer: int, step: float = 1.0, *,
          y: Optional[torch.Tensor] = None, w: Optional[torch.Tensor] = None,
-         gmm: Optional[GMM] = None, eps: float = 0.01, iters: int = 100, debias: bool = True,
-         svgd_h: float = 0.0, device=None):
-    """Outer planning loop (ct_plan).  Returns (u [T,m], s [T+1,n], hist [outer])."""
+         gmm: Optional[GMM] = None, grid: Optional[UtilityGrid] = None, eps: float = 0.01,
+         iters: int = 100, debias: bool = True, svgd_h: float = 0.0, device=None):
+    """Outer planning loop (ct_plan).  flow: "sinkhorn" (y, w), "svgd" (gmm) or
+    "svgd_grid" (grid).  Returns (u [T,m], s [T+1,n], hist [outer])."""
     s0 = _f64(s0)
     u = _f64(u).copy()
     Q = _f64(Q)
@@ -316,10 +396,12 @@ def plan(dynamics: str, s0, u, dt: float, Q, R, flow: str, outer: int, step: flo
     d = Q.shape[0]
     n = s0.shape[0]
     dev = torch.device(device) if device is not None else (
-        y.device if y is not None else gmm.weights.device)
+        y.device if y is not None else gmm.weights.device if gmm is not None else grid.u.device)
     prob = L.PlanProblem(_DYN[dynamics], d, T, float(dt), _dp(s0))
     sk = _opts(d, eps, iters, L.CT_DEBIAS if debias else 0)
-    opts = L.PlanOpts(_FLOW[flow], int(outer), float(step), _dp(Q), _dp(R), sk, float(svgd_h))
+    gdesc = grid.desc() if grid is not None else None
+    opts = L.PlanOpts(_FLOW[flow], int(outer), float(step), _dp(Q), _dp(R), sk, float(svgd_h),
+                      ctypes.pointer(gdesc) if gdesc is not None else None)
     M = 0
     if y is not None:
         y = _req(y, "y", dev)

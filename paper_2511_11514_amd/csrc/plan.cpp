@@ -233,6 +233,7 @@ void rollout(int kind, const Dyn& D, const double* s0, const double* u, int64_t 
 struct PlanLayout {
     float* x;
     float* flow;
+    float* score;   // utility-grid score (CT_FLOW_SVGD_GRID)
     float* value;
     float* pot;
     void* inner;
@@ -246,6 +247,7 @@ PlanLayout plan_layout(void* ws, const ct_plan_problem* p, const ct_plan_opts* o
     const int64_t T = p->T;
     L.x = a.take<float>((size_t)T * p->d);
     L.flow = a.take<float>((size_t)T * p->d);
+    L.score = o->flow == CT_FLOW_SVGD_GRID ? a.take<float>((size_t)T * p->d) : nullptr;
     L.value = a.take<float>(4);
     L.pot = a.take<float>((size_t)(2 * T + 2 * std::max<int64_t>(M, 0)));
     if (o->flow == CT_FLOW_SINKHORN) {
@@ -276,6 +278,8 @@ ct_status plan_validate(const ct_plan_problem* p, const ct_plan_opts* o, const f
             return fail(CT_E_ARG, "plan accepts only CT_DEBIAS and CT_SAFE_LSE Sinkhorn flags");
     } else if (o->flow == CT_FLOW_SVGD) {
         if (!q) return fail(CT_E_ARG, "the Stein flow needs a mixture");
+    } else if (o->flow == CT_FLOW_SVGD_GRID) {
+        if (!o->grid) return fail(CT_E_ARG, "the grid Stein flow needs opts.grid");
     } else {
         return fail(CT_E_ARG, "unknown flow %d", o->flow);
     }
@@ -348,8 +352,15 @@ extern "C" ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, co
             for (int64_t t = 0; t < T; ++t)
                 for (int k = 0; k < d; ++k) tgt[t * n + k] = -(double)T * (double)fh[t * d + k];
         } else {
-            rc = ct_svgd_grad(L.x, T, d, q, o->svgd_h, L.flow, nullptr, nullptr, L.inner,
-                              L.inner_bytes, stream);
+            if (o->flow == CT_FLOW_SVGD) {
+                rc = ct_svgd_grad(L.x, T, d, q, o->svgd_h, L.flow, nullptr, nullptr, L.inner,
+                                  L.inner_bytes, stream);
+            } else {
+                rc = ct_grid_score(L.x, T, d, o->grid, L.score, stream);
+                if (rc) return rc;
+                rc = ct_svgd_grad_score(L.x, T, d, L.score, o->svgd_h, L.flow, nullptr, L.inner,
+                                        L.inner_bytes, stream);
+            }
             if (rc) return rc;
             CT_CHECK_HIP(hipMemcpyAsync(fh.data(), L.flow, sizeof(float) * T * d, hipMemcpyDeviceToHost, st));
             CT_CHECK_HIP(hipStreamSynchronize(st));

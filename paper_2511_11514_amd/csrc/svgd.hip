@@ -1,5 +1,8 @@
 // ct_svgd_grad: Stein variational flow (Sec. II-B, eq. 4) with the RBF kernel
 // and the analytic score of a Gaussian mixture (+ uniform floor).
+// ct_svgd_grad_score: the same flow for a score the caller already holds in
+// device memory (the flow needs only the score, so any unnormalised target
+// works, e.g. a gridded utility through ct_grid_score).
 //
 //   phi_i = 1/T sum_j k_ij [score_j + (2/h)(x_i - x_j)],  k_ij = exp(-|x_i - x_j|^2 / h)
 //
@@ -427,28 +430,26 @@ extern "C" size_t ct_svgd_workspace_size(int64_t T, int32_t d) {
     return sv_layout(nullptr, (int)T, d).bytes;
 }
 
-extern "C" ct_status ct_svgd_grad(const float* x, int64_t T64, int32_t d, const ct_gmm* q, float h,
-                                  float* phi, float* score, float* h_used, void* ws,
-                                  size_t ws_bytes, void* stream) {
-    clear_error();
+namespace ct {
+namespace {
+
+ct_status svgd_check(const float* x, int64_t T64, int32_t d, float h, float* phi, void* ws,
+                     size_t ws_bytes, SvLayout& L) {
     if (d != 2 && d != 3) return fail(CT_E_SHAPE, "d must be 2 or 3 (got %d)", d);
     if (T64 < 1 || T64 > (int64_t(1) << 30)) return fail(CT_E_SHAPE, "T must be in [1, 2^30]");
-    if (!x || !q || !phi) return fail(CT_E_ARG, "x, q and phi must be non-null");
-    if (q->K < 1 || q->K > kMaxK) return fail(CT_E_ARG, "K must be in [1, %d] (got %d)", kMaxK, q->K);
-    if (!q->weights || !q->means || !q->sigmas) return fail(CT_E_ARG, "mixture arrays must be non-null");
-    if (!(q->floor >= 0.f && q->floor < 1.f)) return fail(CT_E_ARG, "floor must be in [0, 1)");
+    if (!x || !phi) return fail(CT_E_ARG, "x and phi must be non-null");
     if (!std::isfinite(h)) return fail(CT_E_ARG, "h must be finite");
-    const int T = (int)T64;
-    if (h <= 0.f && T > 92681) return fail(CT_E_SHAPE, "median bandwidth supports T <= 92681");
+    if (h <= 0.f && T64 > 92681) return fail(CT_E_SHAPE, "median bandwidth supports T <= 92681");
     if (!ws) return fail(CT_E_ARG, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
-    SvLayout L = sv_layout(ws, T, d);
+    L = sv_layout(ws, (int)T64, d);
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    return CT_OK;
+}
 
-    ScoreArgs S{x, T, d, q->K, q->weights, q->means, q->sigmas, q->floor, L.score, score};
-    hipLaunchKernelGGL(k_gmm_score, dim3((T + 255) / 256), dim3(256), 0, st, S);
-    CT_CHECK_HIP(hipGetLastError());
+// Bandwidth, staging and the T x T sum for a score already in device memory.
+ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, float* phi,
+                    float* h_used, const SvLayout& L, hipStream_t st) {
     hipLaunchKernelGGL(k_med_init, dim3(1), dim3(256), 0, st, L.st, L.hist, T);
     CT_CHECK_HIP(hipGetLastError());
     if (h <= 0.f && T > 1) {
@@ -466,7 +467,7 @@ extern "C" ct_status ct_svgd_grad(const float* x, int64_t T64, int32_t d, const 
         }
     }
     const int Tpad = pad_keys(T);
-    hipLaunchKernelGGL(k_svgd_stage, dim3((Tpad + 255) / 256), dim3(256), 0, st, x, L.score, T, Tpad,
+    hipLaunchKernelGGL(k_svgd_stage, dim3((Tpad + 255) / 256), dim3(256), 0, st, x, score, T, Tpad,
                        d, h > 0.f ? h : 0.f, L.st, L.qc, L.krec);
     CT_CHECK_HIP(hipGetLastError());
     SvgdJob J;
@@ -492,4 +493,37 @@ extern "C" ct_status ct_svgd_grad(const float* x, int64_t T64, int32_t d, const 
     CT_CHECK_HIP(hipGetLastError());
     if (tok) profile_end(tok, st, 2, 0, kSvR * 100, J.nqb * J.splits, (double)T * T);
     return CT_OK;
+}
+
+}  // namespace
+}  // namespace ct
+
+extern "C" ct_status ct_svgd_grad(const float* x, int64_t T64, int32_t d, const ct_gmm* q, float h,
+                                  float* phi, float* score, float* h_used, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    clear_error();
+    SvLayout L;
+    ct_status rc = svgd_check(x, T64, d, h, phi, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (!q) return fail(CT_E_ARG, "q must be non-null");
+    if (q->K < 1 || q->K > kMaxK) return fail(CT_E_ARG, "K must be in [1, %d] (got %d)", kMaxK, q->K);
+    if (!q->weights || !q->means || !q->sigmas) return fail(CT_E_ARG, "mixture arrays must be non-null");
+    if (!(q->floor >= 0.f && q->floor < 1.f)) return fail(CT_E_ARG, "floor must be in [0, 1)");
+    const int T = (int)T64;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ScoreArgs S{x, T, d, q->K, q->weights, q->means, q->sigmas, q->floor, L.score, score};
+    hipLaunchKernelGGL(k_gmm_score, dim3((T + 255) / 256), dim3(256), 0, st, S);
+    CT_CHECK_HIP(hipGetLastError());
+    return svgd_flow(x, T, d, L.score, h, phi, h_used, L, st);
+}
+
+extern "C" ct_status ct_svgd_grad_score(const float* x, int64_t T64, int32_t d, const float* score,
+                                        float h, float* phi, float* h_used, void* ws,
+                                        size_t ws_bytes, void* stream) {
+    clear_error();
+    SvLayout L;
+    ct_status rc = svgd_check(x, T64, d, h, phi, ws, ws_bytes, L);
+    if (rc) return rc;
+    if (!score) return fail(CT_E_ARG, "score must be non-null");
+    return svgd_flow(x, (int)T64, d, score, h, phi, h_used, L, static_cast<hipStream_t>(stream));
 }

@@ -146,3 +146,74 @@ def test_plan_ensemble_rejects_bad_arguments_before_launch():
     o = _lib.PlanOpts(_lib.CT_FLOW_SINKHORN, 1, 0.5, dp(Q), dp(R), sk, 0.0)
     assert L.ct_plan_ensemble_workspace_size(ctypes.byref(prob), ctypes.byref(o), 2, 20, 0) > 0
     assert L.ct_plan_ensemble_workspace_size(ctypes.byref(prob), ctypes.byref(o), 0, 20, 0) == 0
+
+
+def test_grid_entry_points_reject_bad_arguments_before_launch():
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    P = ctypes.c_void_p
+
+    def desc(n=(4, 5, 1), lo=(0.0, 0.0, 0.0), hi=(1.0, 2.0, 0.0), u=256, floor=0.0):
+        return _lib.GridDesc((ctypes.c_int32 * 3)(*n), (ctypes.c_float * 3)(*lo),
+                             (ctypes.c_float * 3)(*hi), u, floor)
+
+    def score(g=None, d=2, T=10, x=256, out=256):
+        g = g if g is not None else desc()
+        return L.ct_grid_score(P(x), T, d, ctypes.byref(g), P(out), None)
+
+    assert score(d=4) == _lib.CT_E_SHAPE
+    assert score(T=0) == _lib.CT_E_SHAPE
+    assert score(x=None) == _lib.CT_E_ARG
+    assert score(out=None) == _lib.CT_E_ARG
+    assert score(g=desc(u=None)) == _lib.CT_E_ARG
+    assert score(g=desc(n=(1, 5, 1))) == _lib.CT_E_SHAPE
+    assert score(g=desc(n=(4, 5, 1)), d=3) == _lib.CT_E_SHAPE            # axis 2 has 1 node
+    assert score(g=desc(hi=(1.0, 0.0, 0.0))) == _lib.CT_E_ARG             # hi <= lo on axis 1
+    assert score(g=desc(lo=(float("nan"), 0.0, 0.0))) == _lib.CT_E_ARG
+    assert score(g=desc(floor=-1.0)) == _lib.CT_E_ARG
+    assert L.ct_grid_score(P(256), 10, 2, None, P(256), None) == _lib.CT_E_ARG
+
+    g = desc()
+    n = L.ct_grid_samples_workspace_size(ctypes.byref(g), 2)
+    assert n > 0
+    assert L.ct_grid_samples_workspace_size(ctypes.byref(desc(n=(400, 500, 1))), 2) > n
+    assert L.ct_grid_samples_workspace_size(ctypes.byref(g), 4) == 0
+    assert L.ct_grid_samples_workspace_size(ctypes.byref(desc(n=(1 << 15, 1 << 14, 1))), 2) == 0
+    M = ctypes.c_int64()
+
+    def samples(g=g, y=256, w=256, m=ctypes.byref(M), ws=256, nb=n):
+        return L.ct_grid_samples(ctypes.byref(g), 2, P(y), P(w), m, P(ws), nb, None)
+
+    assert samples(y=None) == _lib.CT_E_ARG
+    assert samples(w=None) == _lib.CT_E_ARG
+    assert samples(m=None) == _lib.CT_E_ARG
+    assert samples(ws=None) == _lib.CT_E_ARG
+    assert samples(ws=257) == _lib.CT_E_WORKSPACE
+    assert samples(nb=n - 1) == _lib.CT_E_WORKSPACE
+    assert samples(g=desc(floor=float("inf"))) == _lib.CT_E_ARG
+
+
+def test_svgd_score_and_grid_plan_reject_bad_arguments_before_launch():
+    import numpy as np
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    P = ctypes.c_void_p
+    n = L.ct_svgd_workspace_size(100, 2)
+    assert L.ct_svgd_grad_score(P(256), 100, 2, None, 0.0, P(256), None, P(256), n, None) == _lib.CT_E_ARG
+    assert L.ct_svgd_grad_score(P(256), 100, 4, P(256), 0.0, P(256), None, P(256), n, None) == _lib.CT_E_SHAPE
+    assert L.ct_svgd_grad_score(P(256), 100, 2, P(256), float("nan"), P(256), None, P(256), n,
+                                None) == _lib.CT_E_ARG
+    assert L.ct_svgd_grad_score(P(256), 100, 2, P(256), 0.0, P(256), None, P(256), n - 1,
+                                None) == _lib.CT_E_WORKSPACE
+    s0 = np.zeros(3)
+    Q, R = np.eye(2), 0.01 * np.eye(2)
+    u = np.zeros((10, 2))
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    prob = _lib.PlanProblem(_lib.CT_DYN_UNICYCLE, 2, 10, 0.05, dp(s0))
+    o = _lib.PlanOpts(_lib.CT_FLOW_SVGD_GRID, 1, 0.05, dp(Q), dp(R), _lib.SinkhornOpts(2, 10, 0.01, 1),
+                      0.0, None)
+    assert L.ct_plan(ctypes.byref(prob), ctypes.byref(o), None, None, 0, None, dp(u), None, None,
+                     P(256), 1 << 30, None) == _lib.CT_E_ARG
+    assert "grid" in L.ct_last_error().decode()
+    assert L.ct_plan_workspace_size(ctypes.byref(prob), ctypes.byref(o), 0) > \
+        L.ct_svgd_workspace_size(10, 2)

@@ -14,7 +14,10 @@ The shapes and distributions stand in for the paper's coverage workloads
   time-equispaced states of a moving robot (Sec. II-A, eq. 1);
 * reference samples: draws from a Gaussian mixture on the unit box, optionally
   mixed with a uniform floor (Sec. II-A: the target given as samples or as a
-  density).
+  density);
+* utility maps: node values on a regular grid over the unit box, a sum of a few
+  random bumps with a rectangular region of zero utility (an obstacle) (Sec. II-A:
+  the target given as a continuous utility function).
 """
 from __future__ import annotations
 
@@ -26,7 +29,7 @@ import numpy as np
 __all__ = [
     "GMM", "gmm_params", "gmm_sample", "random_walk", "uniform_points",
     "positive_weights", "Config", "CONFIGS", "config_inputs", "batch_inputs",
-    "HORIZON_SWEEPS", "horizon_inputs",
+    "HORIZON_SWEEPS", "horizon_inputs", "utility_map",
 ]
 
 
@@ -105,6 +108,34 @@ def random_walk(rng: np.random.Generator, T: int, d: int, momentum: float = 0.98
 
 def uniform_points(rng: np.random.Generator, n: int, d: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     return _f32(rng.uniform(lo, hi, size=(n, d)))
+
+
+def utility_map(rng: np.random.Generator, n, bumps: int = 5, obstacle: bool = True,
+                lo=None, hi=None):
+    """(u, lo, hi): a synthetic utility map on a grid of n = (n_0, ..., n_{d-1})
+    nodes over the box [lo, hi] (default the unit box).  u has shape
+    (n_{d-1}, ..., n_0) (axis 0 fastest in memory): the sum of `bumps` random
+    isotropic bumps (amplitudes U[0.5, 2], centres U[0.15, 0.85] of the box, widths
+    U[0.05, 0.2] of its extent), zeroed on a random axis-aligned box covering about
+    a tenth of the area when `obstacle`.  float32."""
+    d = len(n)
+    lo = np.zeros(d) if lo is None else np.asarray(lo, np.float64)
+    hi = np.ones(d) if hi is None else np.asarray(hi, np.float64)
+    axes = [np.linspace(0.0, 1.0, k) for k in n]
+    mesh = np.meshgrid(*reversed(axes), indexing="ij")        # slowest axis first
+    pts = np.stack(list(reversed(mesh)), axis=-1)              # [..., d], unit coordinates
+    u = np.zeros(tuple(reversed(n)))
+    for _ in range(bumps):
+        a = rng.uniform(0.5, 2.0)
+        c = rng.uniform(0.15, 0.85, d)
+        s = rng.uniform(0.05, 0.2)
+        u += a * np.exp(-np.sum((pts - c) ** 2, axis=-1) / (2.0 * s * s))
+    if obstacle:
+        side = 0.1 ** (1.0 / d)
+        c0 = rng.uniform(0.1, 0.9 - side, d)
+        inside = np.all((pts >= c0) & (pts <= c0 + side), axis=-1)
+        u[inside] = 0.0
+    return _f32(u), _f32(lo), _f32(hi)
 
 
 def positive_weights(rng: np.random.Generator, n: int, lo: float = 0.5, hi: float = 2.0) -> np.ndarray:
