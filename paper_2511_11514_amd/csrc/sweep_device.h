@@ -12,9 +12,11 @@
 // 4 waves either own 4 different query groups (WS = 1), or 2 groups with the
 // keys halved between wave pairs (WS = 2), or one group with the keys split
 // four ways (WS = 4); the WS partial sums are combined through LDS.  Keys are
-// read as wave-uniform 16-byte records (x', y', [z',] h), so they arrive in
-// scalar registers through the scalar cache and feed the VALU directly: one
-// record load serves 64 R pairs and uses no LDS bandwidth.
+// 16-byte records (x', y', [z',] h).  In lagged sweeps each wave stages 64 keys
+// at a time in a private LDS slot (one coalesced vector load, issued a chunk
+// ahead) and reads them back as broadcasts, so a key read serves 64 R pairs and
+// the load latency hides behind the previous chunk's work; safe sweeps read
+// groups of 8 wave-uniform records through the scalar cache.
 //
 // Two accumulation modes:
 //  * safe   : groups of 8 keys, running maximum per query, rescale when it
@@ -128,13 +130,27 @@ template <int D, int R, bool LAGGED, bool BARY>
 __device__ __forceinline__ void sweep_keys(const float4* __restrict__ rec, int k0, int k1,
                                            QueryRegs<D, R>& Q) {
     if (LAGGED) {
+        // 64 keys per wave at a time: one coalesced vector load (the next chunk is
+        // loaded while this one is swept), one LDS write, then broadcast reads.
+        // LDS operations of one wave complete in order, so a wave-private slot
+        // needs no barrier; the wave barriers only keep the compiler from moving
+        // the slot's accesses across the write.
+        __shared__ float4 kbuf[4][64];
+        const int lane = (int)threadIdx.x & 63;
+        float4* slot = kbuf[__builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)];
+        if (k0 >= k1) return;
+        float4 nxt = rec[min(k0 + lane, k1 - 1)];
+        for (int k = k0; k < k1; k += 64) {
+            __builtin_amdgcn_wave_barrier();
+            slot[lane] = nxt;
+            __builtin_amdgcn_wave_barrier();
+            if (k + 64 < k1) nxt = rec[min(k + 64 + lane, k1 - 1)];
+            const int n = min(64, k1 - k);
 #pragma unroll 2
-        for (int k = k0; k < k1; k += 4) {
-            const float4 a = rec[k], b = rec[k + 1], c = rec[k + 2], d = rec[k + 3];
-            pair_lagged<D, R, BARY>(a, Q);
-            pair_lagged<D, R, BARY>(b, Q);
-            pair_lagged<D, R, BARY>(c, Q);
-            pair_lagged<D, R, BARY>(d, Q);
+            for (int j = 0; j < n; j += 8) {
+#pragma unroll
+                for (int g = 0; g < 8; ++g) pair_lagged<D, R, BARY>(slot[j + g], Q);
+            }
         }
     } else {
         for (int k = k0; k < k1; k += 8) {
