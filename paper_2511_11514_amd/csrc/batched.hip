@@ -659,7 +659,7 @@ size_t build_lock(const BLayout& L, const std::vector<BProb>& P, uint32_t flags,
             if (j.splits > 1) {
                 j.part = L.lpart + part;
                 part += (size_t)(2 + d) * j.splits * (size_t)j.nqb * qpb;
-                nm += (j.nq + kBlock - 1) / kBlock;
+                nm += (j.nq + kMergeRows - 1) / kMergeRows;
             }
             jt[i] = j;
             blk[(size_t)k * 3 * B + i] = nb;

@@ -50,6 +50,9 @@ struct Arena {
 // Key records are float4 (x', y', h, 0) for d = 2 and (x', y', z', h) for d = 3,
 // padded with h = -inf records up to nkpad (a multiple of kKeyPad).
 constexpr int kKeyPad = 32;
+// Query rows per block of the separate merge kernels (one per lane of a wave;
+// the block's four waves share the splits).
+constexpr int kMergeRows = 64;
 
 struct Job {
     const float4* qrec;    // [nq] pre-scaled query coordinates (never written)

@@ -2,7 +2,7 @@
 // the same update of many independent problems (the batched path runs two such
 // launches per iteration), each job split over keys so that every block sweeps
 // about the same number of pairs; split jobs are merged by a second kernel.
-// The per-unit work is sweep_unit / merge_rows of sweep_device.h.
+// The per-unit work is sweep_unit / merge_block of sweep_device.h.
 #include <algorithm>
 #include <cmath>
 
@@ -37,16 +37,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tab(TabLaunch L) {
 
 template <int D, bool LAGGED, bool BARY>
 __global__ __launch_bounds__(kBlock) void k_merge_tab(TabLaunch L, int qpb) {
-    __shared__ int flist[kBlock];
-    __shared__ int nflag;
     const int bid = (int)blockIdx.x;
     const int j = __builtin_amdgcn_readfirstlane(owner(L.mrg_end, L.njobs, bid));
     const Job J = L.jobs[j];
-    if (threadIdx.x == 0) nflag = 0;
-    __syncthreads();
-    const int q = (bid - (j ? L.mrg_end[j - 1] : 0)) * kBlock + (int)threadIdx.x;
-    merge_rows<D, LAGGED, BARY>(J, q, J.nqb * qpb, L.kappa, L.inv_kappa, L.inv_sqrt_kappa, flist,
-                                &nflag);
+    const int q0 = (bid - (j ? L.mrg_end[j - 1] : 0)) * kMergeRows;
+    merge_block<D, LAGGED, BARY>(J, q0, J.nqb * qpb, L.kappa, L.inv_kappa, L.inv_sqrt_kappa);
 }
 
 int plan_job_target(Job& j, const Schedule& s, double pairs_per_block) {

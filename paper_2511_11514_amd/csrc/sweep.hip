@@ -21,27 +21,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Launch L) {
                                             sm);
 }
 
-// Merge kernel of the separate-merge mode: blocks of 256 query rows per job
+// Merge kernel of the separate-merge mode: blocks of kMergeRows query rows per job
 // (jobs with a single split were finished by the sweep itself).
 template <int D, bool LAGGED, bool BARY>
 __global__ __launch_bounds__(kBlock) void k_merge(Launch L, int R, int WS) {
-    __shared__ int flist[kBlock];
-    __shared__ int nflag;
     const int bid = (int)blockIdx.x;
     int j = 0, start = 0;
     for (;;) {
         const Job& Jj = L.job[j];
-        const int nb = Jj.splits > 1 ? (Jj.nq + kBlock - 1) / kBlock : 0;
+        const int nb = Jj.splits > 1 ? (Jj.nq + kMergeRows - 1) / kMergeRows : 0;
         if (bid < start + nb || j + 1 == L.njobs) break;
         start += nb;
         ++j;
     }
     const Job& J = L.job[j];
-    if (threadIdx.x == 0) nflag = 0;
-    __syncthreads();
     const int nqpad = J.nqb * 64 * R * (4 / WS);
-    const int q = (bid - start) * kBlock + (int)threadIdx.x;
-    merge_rows<D, LAGGED, BARY>(J, q, nqpad, L.kappa, L.inv_kappa, L.inv_sqrt_kappa, flist, &nflag);
+    merge_block<D, LAGGED, BARY>(J, (bid - start) * kMergeRows, nqpad, L.kappa, L.inv_kappa,
+                                 L.inv_sqrt_kappa);
 }
 
 int plan_job(Job& j, const Schedule& s) {
@@ -123,7 +119,7 @@ static hipError_t launch_merge(int R, int WS, bool lagged, bool bary, const Laun
                                hipStream_t s) {
     int nb = 0;
     for (int j = 0; j < L.njobs; ++j)
-        if (L.job[j].splits > 1) nb += (L.job[j].nq + kBlock - 1) / kBlock;
+        if (L.job[j].splits > 1) nb += (L.job[j].nq + kMergeRows - 1) / kMergeRows;
     if (nb == 0) return hipSuccess;
     if (lagged) {
         if (bary) hipLaunchKernelGGL((k_merge<D, true, true>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);

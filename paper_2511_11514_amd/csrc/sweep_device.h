@@ -449,30 +449,56 @@ __device__ __forceinline__ void sweep_unit(const Job& J, int qb, int split, floa
     }
 }
 
-// Separate merge: one thread per query row combines the partials of every split
-// (fixed order), then finishes or flags the row; flagged rows are recomputed by
-// the block.  Used when many small blocks make per-block merging expensive.
+// Separate merge of the kMergeRows query rows q0.. of a job: the block's four
+// waves take every fourth split in increasing order, their partials meet in LDS
+// in wave order (a fixed order, so results are deterministic), wave 0 finishes
+// or flags the rows, and flagged rows are recomputed by the whole block.
 template <int D, bool LAGGED, bool BARY>
-__device__ __forceinline__ void merge_rows(const Job& J, int q, int nqpad, float kappa,
-                                           float inv_kappa, float inv_sqrt_kappa, int* flist,
-                                           int* nflag) {
+__device__ __forceinline__ void merge_block(const Job& J, int q0, int nqpad, float kappa,
+                                            float inv_kappa, float inv_sqrt_kappa) {
+    constexpr int NC = 2 + D;
+    __shared__ float red[3 * NC * kMergeRows];
+    __shared__ int flist[kMergeRows];
+    __shared__ int nflag;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = (int)threadIdx.x & 63;
+    const int q = q0 + lane;
+    if (threadIdx.x == 0) nflag = 0;
     const size_t cstride = (size_t)J.splits * nqpad;
+    float m = LAGGED ? (q < J.nq ? -J.qpot[q] * kappa : 0.f) : -FLT_MAX;
+    float s = 0.f, b[D];
+#pragma unroll
+    for (int t = 0; t < D; ++t) b[t] = 0.f;
     if (q < J.nq) {
-        float m = LAGGED ? -J.qpot[q] * kappa : -FLT_MAX;
-        float s = 0.f, b[D];
-        for (int t = 0; t < D; ++t) b[t] = 0.f;
-        for (int sp = 0; sp < J.splits; ++sp) {
+        for (int sp = wave; sp < J.splits; sp += 4) {
             const float* P = J.part + (size_t)sp * nqpad + q;
             float b2[D];
             if (BARY)
                 for (int t = 0; t < D; ++t) b2[t] = P[(2 + t) * cstride];
             combine<D, LAGGED, BARY>(m, s, b, LAGGED ? m : P[0], P[cstride], b2);
         }
-        finish_or_flag<D, LAGGED>(J, q, m, s, b, flist, nflag, kappa, inv_kappa, inv_sqrt_kappa);
+    }
+    if (wave > 0) {
+        float* S = red + (wave - 1) * NC * kMergeRows + lane;
+        S[0] = m;
+        S[kMergeRows] = s;
+        if (BARY)
+            for (int t = 0; t < D; ++t) S[(2 + t) * kMergeRows] = b[t];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        for (int w = 1; w < 4; ++w) {
+            const float* S = red + (w - 1) * NC * kMergeRows + lane;
+            float b2[D];
+            if (BARY)
+                for (int t = 0; t < D; ++t) b2[t] = S[(2 + t) * kMergeRows];
+            combine<D, LAGGED, BARY>(m, s, b, S[0], S[kMergeRows], b2);
+        }
+        finish_or_flag<D, LAGGED>(J, q, m, s, b, flist, &nflag, kappa, inv_kappa, inv_sqrt_kappa);
     }
     if (LAGGED) {
         __syncthreads();
-        const int n = *nflag;
+        const int n = nflag;
         if (n > 0) rescue_rows<D, BARY>(J, flist, n, kappa, inv_kappa, inv_sqrt_kappa);
     }
 }
