@@ -13,17 +13,10 @@ namespace {
 
 constexpr int kMaxDim = 8;
 
-// y = M x for an r x c row-major matrix.
-void matvec(const double* M, const double* x, double* y, int r, int c) {
-    for (int i = 0; i < r; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < c; ++j) s += M[i * c + j] * x[j];
-        y[i] = s;
-    }
-}
-
 // In-place Cholesky factor of an SPD m x m matrix; false if not positive definite.
-bool cholesky(double* H, int m) {
+template <int MM>
+inline bool cholesky(double* H, int m_rt) {
+    const int m = MM > 0 ? MM : m_rt;
     for (int j = 0; j < m; ++j) {
         double d = H[j * m + j];
         for (int k = 0; k < j; ++k) d -= H[j * m + k] * H[j * m + k];
@@ -40,7 +33,10 @@ bool cholesky(double* H, int m) {
 }
 
 // Solve (L L^T) X = B for an m x c right-hand side in place.
-void chol_solve(const double* L, double* B, int m, int c) {
+template <int MM, int CC>
+inline void chol_solve(const double* L, double* B, int m_rt, int c_rt) {
+    const int m = MM > 0 ? MM : m_rt;
+    const int c = CC > 0 ? CC : c_rt;
     for (int col = 0; col < c; ++col) {
         for (int i = 0; i < m; ++i) {
             double s = B[i * c + col];
@@ -55,28 +51,36 @@ void chol_solve(const double* L, double* B, int m, int c) {
     }
 }
 
-}  // namespace
-
 // Backward Riccati recursion with the affine tracking term, then forward rollout.
 // With S = dt Q + P_{t+1}, s = dt Q a_t + p_{t+1}, H = dt R + B'SB (discrete A, B):
-//   K_t = H^-1 B'SA, k_t = H^-1 B's,  P_t = A'SA - A'SB K_t,  p_t = A'(s - SB k_t),
+//   K_t = H^-1 B'SA, k_t = H^-1 B's,  P_t = A'(SA - SB K_t),  p_t = A'(s - SB k_t),
 //   v_t = -K_t z_t + k_t,  z_{t+1} = A z_t + B v_t.
-ct_status lqr_solve(int64_t T, int n, int m, double dt, const double* A, const double* B,
-                    const double* a, const double* Q, const double* R, double* v, double* z) {
+// NN, MM > 0 fix the state and control sizes at compile time (the planner's
+// dynamics); 0 takes them from n_rt, m_rt.
+template <int NN, int MM>
+ct_status lqr_core(int64_t T, int n_rt, int m_rt, double dt, const double* A, const double* B,
+                   const double* a, const double* Q, const double* R, double* v, double* z) {
+    const int n = NN > 0 ? NN : n_rt;
+    const int m = MM > 0 ? MM : m_rt;
     std::vector<double> Ks((size_t)T * m * n), ks((size_t)T * m);
     double P[kMaxDim * kMaxDim] = {0}, p[kMaxDim] = {0};
     double Ad[kMaxDim * kMaxDim], Bd[kMaxDim * kMaxDim], S[kMaxDim * kMaxDim], s[kMaxDim];
-    double SB[kMaxDim * kMaxDim], SA[kMaxDim * kMaxDim], H[kMaxDim * kMaxDim], G[kMaxDim * (kMaxDim + 1)];
+    double SB[kMaxDim * kMaxDim], SA[kMaxDim * kMaxDim], H[kMaxDim * kMaxDim];
+    double G[kMaxDim * (kMaxDim + 1)], SBK[kMaxDim * kMaxDim], Pn[kMaxDim * kMaxDim];
     for (int64_t t = T - 1; t >= 0; --t) {
         const double* At = A + (size_t)t * n * n;
         const double* Bt = B + (size_t)t * n * m;
+        const double* at = a + (size_t)t * n;
         for (int i = 0; i < n; ++i) {
             for (int j = 0; j < n; ++j) Ad[i * n + j] = (i == j ? 1.0 : 0.0) + dt * At[i * n + j];
             for (int j = 0; j < m; ++j) Bd[i * m + j] = dt * Bt[i * m + j];
         }
         for (int i = 0; i < n * n; ++i) S[i] = dt * Q[i] + P[i];
-        matvec(Q, a + (size_t)t * n, s, n, n);
-        for (int i = 0; i < n; ++i) s[i] = dt * s[i] + p[i];
+        for (int i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j) acc += Q[i * n + j] * at[j];
+            s[i] = dt * acc + p[i];
+        }
         // SB = S Bd (n x m), SA = S Ad (n x n)
         for (int i = 0; i < n; ++i) {
             for (int j = 0; j < m; ++j) {
@@ -106,26 +110,27 @@ ct_status lqr_solve(int64_t T, int n, int m, double dt, const double* A, const d
             for (int k = 0; k < n; ++k) acc += Bd[k * m + i] * s[k];
             G[i * (n + 1) + n] = acc;
         }
-        if (!cholesky(H, m))
+        if (!cholesky<MM>(H, m))
             return fail(CT_E_UNSUPPORTED, "Riccati step %lld: dt R + B'SB is not positive definite",
                         (long long)t);
-        chol_solve(H, G, m, n + 1);
+        chol_solve<MM, (NN > 0 ? NN + 1 : 0)>(H, G, m, n + 1);
         double* Kt = Ks.data() + (size_t)t * m * n;
         double* kt = ks.data() + (size_t)t * m;
         for (int i = 0; i < m; ++i) {
             for (int j = 0; j < n; ++j) Kt[i * n + j] = G[i * (n + 1) + j];
             kt[i] = G[i * (n + 1) + n];
         }
-        // P = Ad' S Ad - Ad' S Bd K ;  p = Ad' (s - S Bd k)
-        double Pn[kMaxDim * kMaxDim];
+        // P = Ad' (S Ad - S Bd K) ;  p = Ad' (s - S Bd k)
+        for (int k = 0; k < n; ++k)
+            for (int j = 0; j < n; ++j) {
+                double acc = SA[k * n + j];
+                for (int l = 0; l < m; ++l) acc -= SB[k * m + l] * Kt[l * n + j];
+                SBK[k * n + j] = acc;
+            }
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 double acc = 0.0;
-                for (int k = 0; k < n; ++k) {
-                    double sbk = 0.0;
-                    for (int l = 0; l < m; ++l) sbk += SB[k * m + l] * Kt[l * n + j];
-                    acc += Ad[k * n + i] * (SA[k * n + j] - sbk);
-                }
+                for (int k = 0; k < n; ++k) acc += Ad[k * n + i] * SBK[k * n + j];
                 Pn[i * n + j] = acc;
             }
         for (int i = 0; i < n; ++i)
@@ -167,6 +172,16 @@ ct_status lqr_solve(int64_t T, int n, int m, double dt, const double* A, const d
             for (int i = 0; i < n; ++i) z[(size_t)(t + 1) * n + i] = zt[i];
     }
     return CT_OK;
+}
+
+}  // namespace
+
+ct_status lqr_solve(int64_t T, int n, int m, double dt, const double* A, const double* B,
+                    const double* a, const double* Q, const double* R, double* v, double* z) {
+    if (n == 3 && m == 2) return lqr_core<3, 2>(T, n, m, dt, A, B, a, Q, R, v, z);  // unicycle
+    if (n == 4 && m == 2) return lqr_core<4, 2>(T, n, m, dt, A, B, a, Q, R, v, z);  // 2-D point mass
+    if (n == 6 && m == 3) return lqr_core<6, 3>(T, n, m, dt, A, B, a, Q, R, v, z);  // 3-D point mass
+    return lqr_core<0, 0>(T, n, m, dt, A, B, a, Q, R, v, z);
 }
 
 namespace {
