@@ -126,15 +126,27 @@ __global__ __launch_bounds__(256) void k_med_init(MedState* st, unsigned long lo
     }
 }
 
-// Histogram of the squared-distance bit patterns of pairs i < j matching each target's prefix.
+// Histogram of the squared-distance bit patterns of pairs i < j matching each
+// target's prefix.  A block takes 256 rows i against 256 / sub columns j (staged
+// in LDS); tiles below the diagonal are skipped.  Narrow column tiles (sub = 4)
+// give small problems enough blocks; wide ones amortise the per-block clearing
+// and flushing of the histogram when there are many tiles.
+__host__ __device__ constexpr int med_sub(int nt) { return nt * (nt + 1) / 2 < 1024 ? 4 : 1; }
+
 template <int D>
 __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, int T, int pass,
                                                   const MedState* __restrict__ st,
                                                   unsigned long long* __restrict__ hist) {
     __shared__ unsigned h[2][kMedBins];
+    __shared__ float4 cj[256];
     const int nt = (T + 255) / 256;
-    const int bi = blockIdx.x % nt, bj = blockIdx.x / nt;
-    if (bj < bi) return;
+    const int nsub = med_sub(nt), jw = 256 / nsub;
+    const int bi = blockIdx.x % nt;
+    const int rest = blockIdx.x / nt;
+    const int bj = rest / nsub, sub = rest % nsub;
+    const int j0 = bj * 256 + sub * jw;
+    if (bj < bi || j0 >= T) return;
+    const int j1 = min(T, j0 + jw);
     const MedPass P = med_pass(pass);
     const unsigned pa = st->prefix[0], pb = st->prefix[1];
     const bool two = pa != pb;
@@ -143,14 +155,13 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
         h[0][k] = 0u;
         h[1][k] = 0u;
     }
+    if ((int)threadIdx.x < j1 - j0) cj[threadIdx.x] = c[j0 + threadIdx.x];
     __syncthreads();
     const int i = bi * 256 + (int)threadIdx.x;
-    if (i < T) {
+    if (i < T && i < j1 - 1) {
         const float4 xi = c[i];
-        const int j0 = bj * 256;
-        const int j1 = min(T, j0 + 256);
-        for (int j = j0; j < j1; ++j) {
-            const float4 xj = c[j];
+        for (int j = max(j0, i + 1); j < j1; ++j) {
+            const float4 xj = cj[j - j0];
             const float dx = xi.x - xj.x, dy = xi.y - xj.y;
             float cc = dy * dy;
             if (D == 3) {
@@ -158,12 +169,10 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
                 cc = __builtin_fmaf(dz, dz, cc);
             }
             cc = __builtin_fmaf(dx, dx, cc);
-            if (j > i) {
-                const unsigned v = __float_as_uint(cc);
-                const unsigned bin = (v >> P.shift) & (unsigned)(nb - 1);
-                if ((v & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
-                if (two && (v & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
-            }
+            const unsigned v = __float_as_uint(cc);
+            const unsigned bin = (v >> P.shift) & (unsigned)(nb - 1);
+            if ((v & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
+            if (two && (v & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
         }
     }
     __syncthreads();
@@ -173,46 +182,52 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
     }
 }
 
-// Locate each target's bin, extend its prefix, clear the histograms.  The bins
-// are scanned by the whole block: per-thread chunk sums, a serial scan of the
-// 256 chunk sums in LDS, then the owning chunk's bins.
+// Locate each target's bin, extend its prefix, clear the histograms.  Each
+// thread holds a run of bins; a block-wide prefix sum of the run totals (wave
+// scans, then the wave totals) tells which thread holds the target rank, and
+// that thread walks its own bins.
 __global__ __launch_bounds__(256) void k_med_select(MedState* st, unsigned long long* hist,
                                                     int pass, int T) {
-    __shared__ unsigned long long csum[256];
-    __shared__ int s_chunk;
-    __shared__ unsigned long long s_before;
+    __shared__ unsigned long long wsum[4];
     const MedPass P = med_pass(pass);
     const int nb = 1 << P.bits;
     const int per = nb / 256;          // bins per thread (16, 8 or 1)
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const bool two = st->prefix[0] != st->prefix[1];
     for (int t = 0; t < 2; ++t) {
         const unsigned long long* H = hist + ((two && t == 1) ? kMedBins : 0);
+        unsigned long long v[16];
         unsigned long long loc = 0;
-        for (int k = 0; k < per; ++k) loc += H[threadIdx.x * per + k];
-        csum[threadIdx.x] = loc;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned long long r = st->rank[t];
-            unsigned long long cum = 0;
-            int c = 0;
-            for (; c < 255; ++c) {
-                if (r < cum + csum[c]) break;
-                cum += csum[c];
-            }
-            s_chunk = c;
-            s_before = cum;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v[k] = k < per ? H[threadIdx.x * per + k] : 0ull;
+            loc += v[k];
         }
+        unsigned long long inc = loc;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (lane == 63) wsum[wave] = inc;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const unsigned long long r = st->rank[t];
-            unsigned long long cum = s_before;
-            int b = s_chunk * per;
-            const int bend = b + per - 1;
-            for (; b < bend; ++b) {
-                if (r < cum + H[b]) break;
-                cum += H[b];
+        unsigned long long before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        const unsigned long long excl = before + inc - loc;
+        const unsigned long long r = st->rank[t];
+        __syncthreads();               // every thread has read the rank before it changes
+        // the owner of the rank (the last thread if the rank exceeds the count)
+        if ((r >= excl && r < excl + loc) || (threadIdx.x == 255 && r >= excl + loc)) {
+            unsigned long long cum = excl;
+            int b = 0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k == b && k < per - 1 && r >= cum + v[k]) {
+                    cum += v[k];
+                    b = k + 1;
+                }
             }
-            st->prefix[t] |= (unsigned)b << P.shift;
+            st->prefix[t] |= (unsigned)(threadIdx.x * per + b) << P.shift;
             st->rank[t] = r - cum;
         }
         __syncthreads();
@@ -303,11 +318,32 @@ __global__ __launch_bounds__(256) void k_svgd_sum(SvgdJob J) {
     const int k0 = min(J.Tpad, split * J.kps);
     const int k1 = min(J.Tpad, k0 + J.kps);
     constexpr int NR = KeyRec<D>::N;
-#pragma unroll 2
-    for (int k = k0; k < k1; ++k) {
-        const float4 r0 = J.krec[(size_t)k * NR];
+    // keys staged 64 at a time in a wave-private LDS slot (one coalesced load per
+    // chunk, issued while the previous chunk is summed; broadcast reads)
+    __shared__ float4 kbuf[4][64 * NR];
+    float4* slot = kbuf[wave];
+    float4 n0 = make_float4(0.f, 0.f, 0.f, 0.f), n1 = n0;
+    if (k0 < k1) {
+        const size_t kk = (size_t)min(k0 + lane, k1 - 1) * NR;
+        n0 = J.krec[kk];
+        if (D == 3) n1 = J.krec[kk + 1];
+    }
+    for (int kc = k0; kc < k1; kc += 64) {
+        __builtin_amdgcn_wave_barrier();
+        slot[lane * NR] = n0;
+        if (D == 3) slot[lane * NR + 1] = n1;
+        __builtin_amdgcn_wave_barrier();
+        if (kc + 64 < k1) {
+            const size_t kk = (size_t)min(kc + 64 + lane, k1 - 1) * NR;
+            n0 = J.krec[kk];
+            if (D == 3) n1 = J.krec[kk + 1];
+        }
+        const int n = min(64, k1 - kc);
+#pragma unroll 4
+    for (int kq = 0; kq < n; ++kq) {
+        const float4 r0 = slot[kq * NR];
         float4 r1 = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (D == 3) r1 = J.krec[(size_t)k * NR + 1];
+        if (D == 3) r1 = slot[kq * NR + 1];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const float dx = q[r][0] - r0.x, dy = q[r][1] - r0.y;
@@ -332,6 +368,7 @@ __global__ __launch_bounds__(256) void k_svgd_sum(SvgdJob J) {
             if (D == 3) b[r][2] = __builtin_fmaf(p, dz, b[r][2]);
         }
     }
+    }
     const int nqpad = J.nqb * 256 * R;
     const size_t cs = (size_t)J.splits * nqpad;
 #pragma unroll
@@ -345,24 +382,43 @@ __global__ __launch_bounds__(256) void k_svgd_sum(SvgdJob J) {
     }
 }
 
-// phi_i = (A_i + (2/h)(1/s) B_i) / T with s = sqrt(log2(e)/h).
+// phi_i = (A_i + (2/h)(1/s) B_i) / T with s = sqrt(log2(e)/h).  A block takes 64
+// rows; its four waves take every fourth split and meet in LDS in wave order.
+constexpr int kSvMergeRows = 64;
+
 template <int D>
 __global__ __launch_bounds__(256) void k_svgd_merge(SvgdJob J, int R) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ float red[3][2 * D][kSvMergeRows];
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int i = (int)blockIdx.x * kSvMergeRows + lane;
     const float h = J.st->h;
-    if (i == 0 && J.h_used) *J.h_used = h;
-    if (i >= J.T) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && J.h_used) *J.h_used = h;
     const int nqpad = J.nqb * 256 * R;
     const size_t cs = (size_t)J.splits * nqpad;
     float a[D], b[D];
     for (int t = 0; t < D; ++t) a[t] = b[t] = 0.f;
-    for (int sp = 0; sp < J.splits; ++sp) {
-        const float* P = J.part + (size_t)sp * nqpad + i;
-        for (int t = 0; t < D; ++t) {
-            a[t] += P[t * cs];
-            b[t] += P[(D + t) * cs];
+    if (i < J.T) {
+        for (int sp = wave; sp < J.splits; sp += 4) {
+            const float* P = J.part + (size_t)sp * nqpad + i;
+            for (int t = 0; t < D; ++t) {
+                a[t] += P[t * cs];
+                b[t] += P[(D + t) * cs];
+            }
         }
     }
+    if (wave > 0) {
+        for (int t = 0; t < D; ++t) {
+            red[wave - 1][t][lane] = a[t];
+            red[wave - 1][D + t][lane] = b[t];
+        }
+    }
+    __syncthreads();
+    if (wave != 0 || i >= J.T) return;
+    for (int w = 0; w < 3; ++w)
+        for (int t = 0; t < D; ++t) {
+            a[t] += red[w][t][lane];
+            b[t] += red[w][D + t][lane];
+        }
     const double s = sqrt(kLog2eD / (double)h);
     const float cb = (float)(2.0 / ((double)h * s));
     const float invT = 1.0f / (float)J.T;
@@ -458,9 +514,11 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
         const int nt = (T + 255) / 256;
         for (int pass = 0; pass < 3; ++pass) {
             if (d == 2)
-                hipLaunchKernelGGL(k_med_hist<2>, dim3(nt * nt), dim3(256), 0, st, L.cmed, T, pass, L.st, L.hist);
+                hipLaunchKernelGGL(k_med_hist<2>, dim3(nt * nt * med_sub(nt)), dim3(256), 0, st, L.cmed,
+                                   T, pass, L.st, L.hist);
             else
-                hipLaunchKernelGGL(k_med_hist<3>, dim3(nt * nt), dim3(256), 0, st, L.cmed, T, pass, L.st, L.hist);
+                hipLaunchKernelGGL(k_med_hist<3>, dim3(nt * nt * med_sub(nt)), dim3(256), 0, st, L.cmed,
+                                   T, pass, L.st, L.hist);
             CT_CHECK_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.st, L.hist, pass, T);
             CT_CHECK_HIP(hipGetLastError());
@@ -487,9 +545,11 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
         hipLaunchKernelGGL((k_svgd_sum<3, kSvR>), dim3(J.nqb * J.splits), dim3(256), 0, st, J);
     CT_CHECK_HIP(hipGetLastError());
     if (d == 2)
-        hipLaunchKernelGGL(k_svgd_merge<2>, dim3((T + 255) / 256), dim3(256), 0, st, J, kSvR);
+        hipLaunchKernelGGL(k_svgd_merge<2>, dim3((T + kSvMergeRows - 1) / kSvMergeRows), dim3(256), 0,
+                           st, J, kSvR);
     else
-        hipLaunchKernelGGL(k_svgd_merge<3>, dim3((T + 255) / 256), dim3(256), 0, st, J, kSvR);
+        hipLaunchKernelGGL(k_svgd_merge<3>, dim3((T + kSvMergeRows - 1) / kSvMergeRows), dim3(256), 0,
+                           st, J, kSvR);
     CT_CHECK_HIP(hipGetLastError());
     if (tok) profile_end(tok, st, 2, 0, kSvR * 100, J.nqb * J.splits, (double)T * T);
     return CT_OK;
