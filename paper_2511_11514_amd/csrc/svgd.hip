@@ -12,12 +12,16 @@
 //   k_med_hist / k_med_select   exact median of the T(T-1)/2 squared distances
 //                 (i < j) by a three-pass radix selection on their float32 bit
 //                 patterns (12 + 11 + 8 bits), both middle ranks tracked so an
-//                 even count takes the mean of the two middle distances;
+//                 even count takes the mean of the two middle distances; for
+//                 large T the same selection runs over the pairs inside a
+//                 bracket found on a sample (k_med_sample / k_med_bracket), with
+//                 the full selection as the fallback;
 //   k_svgd_stage  bandwidth h = med^2 / ln T (or the caller's h), coordinates
 //                 pre-scaled by sqrt(log2(e)/h) so k_ij = 2^-|x'_i - x'_j|^2;
 //   k_svgd_sum / k_svgd_merge   the T x T sum, split over keys like the Sinkhorn
 //                 sweep (keys read as wave-uniform records), fixed-order merge.
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 
 #include "ct_internal.h"
@@ -101,7 +105,40 @@ struct MedState {
     unsigned prefix[2];          // bits of the target values fixed so far
     float h;                     // bandwidth
     float med;
+    int mode;                    // 0: select over all pairs, 1: over the bracket's candidates
+    unsigned long long below;    // pairs below the bracket
+    unsigned long long ncand;    // pairs inside the bracket (may exceed the buffer)
 };
+
+// Large T: an exact selection over a bracket.  kMedSample pseudo-random pairs
+// give the bracket [lo, hi] (their quantiles 1/2 -+ 4 standard errors); one pass
+// over all pairs counts those below lo and collects those inside; the targets'
+// ranks among the candidates are then selected exactly.  If a target falls
+// outside the bracket or the candidates overflow their buffer, the selection
+// runs over all pairs instead (same result, three full passes).
+constexpr int kMedSample = 1 << 20;
+constexpr int kBracketMinT = 11000;
+constexpr int kCandLds = 4096;
+constexpr unsigned long long kSampleLo = 522240;   // floor((1/2 - 4 * 0.5 / 1024) * 2^20)
+constexpr unsigned long long kSampleHi = 526335;   // ceil((1/2 + 4 * 0.5 / 1024) * 2^20) - 1
+
+__host__ __device__ inline unsigned long long med_pairs(int T) {
+    return (unsigned long long)T * (unsigned long long)(T - 1) / 2;
+}
+__host__ __device__ inline unsigned long long cand_cap(int T) {
+    return (unsigned long long)(0.008 * (double)med_pairs(T)) + 65536ull;
+}
+
+template <int D>
+__device__ __forceinline__ float sqdist(const float4& a, const float4& b) {
+    const float dx = a.x - b.x, dy = a.y - b.y;
+    float cc = dy * dy;
+    if (D == 3) {
+        const float dz = a.z - b.z;
+        cc = __builtin_fmaf(dz, dz, cc);
+    }
+    return __builtin_fmaf(dx, dx, cc);
+}
 
 struct MedPass {
     int shift, bits;             // bins = bits >> shift & (2^bits - 1)
@@ -123,7 +160,40 @@ __global__ __launch_bounds__(256) void k_med_init(MedState* st, unsigned long lo
         st->prefix[0] = st->prefix[1] = 0u;
         st->h = 1.f;
         st->med = 0.f;
+        st->mode = 0;
+        st->below = 0ull;
+        st->ncand = 0ull;
     }
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood 2014) as the sample's index hash.
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(64) void k_sample_init(MedState* sst) {
+    if (threadIdx.x == 0) {
+        sst->rank[0] = kSampleLo;
+        sst->rank[1] = kSampleHi;
+        sst->prefix[0] = sst->prefix[1] = 0u;
+        sst->mode = 0;
+    }
+}
+
+// Squared distances of kMedSample pseudo-random pairs i != j (T >= 2).
+template <int D>
+__global__ __launch_bounds__(256) void k_med_sample(const float4* __restrict__ c, int T,
+                                                    float* __restrict__ out) {
+    const int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (k >= kMedSample) return;
+    const unsigned long long z = mix64((unsigned long long)k);
+    const int i = (int)((z & 0xFFFFFFFFull) % (unsigned long long)T);
+    int j = (int)((z >> 32) % (unsigned long long)T);
+    if (j == i) j = (j + 1) % T;
+    out[k] = sqdist<D>(c[i], c[j]);
 }
 
 // Histogram of the squared-distance bit patterns of pairs i < j matching each
@@ -145,7 +215,7 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
     const int rest = blockIdx.x / nt;
     const int bj = rest / nsub, sub = rest % nsub;
     const int j0 = bj * 256 + sub * jw;
-    if (bj < bi || j0 >= T) return;
+    if (bj < bi || j0 >= T || st->mode != 0) return;
     const int j1 = min(T, j0 + jw);
     const MedPass P = med_pass(pass);
     const unsigned pa = st->prefix[0], pb = st->prefix[1];
@@ -161,15 +231,7 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
     if (i < T && i < j1 - 1) {
         const float4 xi = c[i];
         for (int j = max(j0, i + 1); j < j1; ++j) {
-            const float4 xj = cj[j - j0];
-            const float dx = xi.x - xj.x, dy = xi.y - xj.y;
-            float cc = dy * dy;
-            if (D == 3) {
-                const float dz = xi.z - xj.z;
-                cc = __builtin_fmaf(dz, dz, cc);
-            }
-            cc = __builtin_fmaf(dx, dx, cc);
-            const unsigned v = __float_as_uint(cc);
+            const unsigned v = __float_as_uint(sqdist<D>(xi, cj[j - j0]));
             const unsigned bin = (v >> P.shift) & (unsigned)(nb - 1);
             if ((v & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
             if (two && (v & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
@@ -182,13 +244,126 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
     }
 }
 
+// The same histogram over a flat array of squared distances: n0 values, or
+// min(*count, cap) when count is given.  Runs only when gate < 0 or st->mode == gate.
+__global__ __launch_bounds__(256) void k_flat_hist(const float* __restrict__ v, int n0,
+                                                   const unsigned long long* count,
+                                                   unsigned long long cap, int pass,
+                                                   const MedState* st, int gate,
+                                                   unsigned long long* __restrict__ hist) {
+    __shared__ unsigned h[2][kMedBins];
+    if (gate >= 0 && st->mode != gate) return;
+    const long long n = count ? (long long)min(*count, cap) : (long long)n0;
+    const MedPass P = med_pass(pass);
+    const unsigned pa = st->prefix[0], pb = st->prefix[1];
+    const bool two = pa != pb;
+    const int nb = 1 << P.bits;
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        h[0][k] = 0u;
+        h[1][k] = 0u;
+    }
+    __syncthreads();
+    for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) {
+        const unsigned u = __float_as_uint(v[k]);
+        const unsigned bin = (u >> P.shift) & (unsigned)(nb - 1);
+        if ((u & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
+        if (two && (u & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        if (h[0][k]) atomicAdd(&hist[k], (unsigned long long)h[0][k]);
+        if (two && h[1][k]) atomicAdd(&hist[kMedBins + k], (unsigned long long)h[1][k]);
+    }
+}
+
+// One pass over all pairs i < j (tiled as k_med_hist): count the pairs below the
+// bracket [lo, hi] found on the sample, collect those inside (staged in LDS,
+// one global append per block; overflow of the LDS stage appends directly).
+template <int D>
+__global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ c, int T,
+                                                     const MedState* __restrict__ sst,
+                                                     MedState* st, float* __restrict__ cand,
+                                                     unsigned long long cap) {
+    __shared__ float4 cj[256];
+    __shared__ float lc[kCandLds];
+    __shared__ unsigned ln;
+    __shared__ unsigned red[256];
+    __shared__ unsigned long long base;
+    const int nt = (T + 255) / 256;
+    const int nsub = med_sub(nt), jw = 256 / nsub;
+    const int bi = blockIdx.x % nt;
+    const int rest = blockIdx.x / nt;
+    const int bj = rest / nsub, sub = rest % nsub;
+    const int j0 = bj * 256 + sub * jw;
+    if (bj < bi || j0 >= T) return;
+    const int j1 = min(T, j0 + jw);
+    const unsigned lo = sst->prefix[0], hi = sst->prefix[1];
+    if (threadIdx.x == 0) ln = 0u;
+    if ((int)threadIdx.x < j1 - j0) cj[threadIdx.x] = c[j0 + threadIdx.x];
+    __syncthreads();
+    unsigned below = 0u;
+    const int i = bi * 256 + (int)threadIdx.x;
+    if (i < T && i < j1 - 1) {
+        const float4 xi = c[i];
+        for (int j = max(j0, i + 1); j < j1; ++j) {
+            const float d2 = sqdist<D>(xi, cj[j - j0]);
+            const unsigned u = __float_as_uint(d2);
+            below += u < lo ? 1u : 0u;
+            if (u >= lo && u <= hi) {
+                const unsigned k = atomicAdd(&ln, 1u);
+                if (k < (unsigned)kCandLds) {
+                    lc[k] = d2;
+                } else {
+                    const unsigned long long g = atomicAdd(&st->ncand, 1ull);
+                    if (g < cap) cand[g] = d2;
+                }
+            }
+        }
+    }
+    red[threadIdx.x] = below;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    const unsigned n = min(ln, (unsigned)kCandLds);
+    if (threadIdx.x == 0) {
+        if (red[0]) atomicAdd(&st->below, (unsigned long long)red[0]);
+        base = n ? atomicAdd(&st->ncand, (unsigned long long)n) : 0ull;
+    }
+    __syncthreads();
+    for (unsigned k = threadIdx.x; k < n; k += 256)
+        if (base + k < cap) cand[base + k] = lc[k];
+}
+
+// Use the candidates if both targets fall inside the bracket and none was lost.
+__global__ __launch_bounds__(64) void k_med_decide(MedState* st, int T, unsigned long long cap) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long n = med_pairs(T);
+    const unsigned long long ra = n ? (n - 1) / 2 : 0, rb = n / 2;
+    const unsigned long long below = st->below, nc = st->ncand;
+    if (nc <= cap && below <= ra && rb < below + nc) {
+        st->mode = 1;
+        st->rank[0] = ra - below;
+        st->rank[1] = rb - below;
+    } else {
+        st->mode = 0;
+        st->rank[0] = ra;
+        st->rank[1] = rb;
+    }
+    st->prefix[0] = st->prefix[1] = 0u;
+}
+
 // Locate each target's bin, extend its prefix, clear the histograms.  Each
 // thread holds a run of bins; a block-wide prefix sum of the run totals (wave
 // scans, then the wave totals) tells which thread holds the target rank, and
 // that thread walks its own bins.
+// Runs only when gate < 0 or st->mode == gate; `finish` turns the final pass's
+// values into the median and the bandwidth.
 __global__ __launch_bounds__(256) void k_med_select(MedState* st, unsigned long long* hist,
-                                                    int pass, int T) {
+                                                    int pass, int T, int gate, int finish) {
     __shared__ unsigned long long wsum[4];
+    if (gate >= 0 && st->mode != gate) return;
     const MedPass P = med_pass(pass);
     const int nb = 1 << P.bits;
     const int per = nb / 256;          // bins per thread (16, 8 or 1)
@@ -232,7 +407,7 @@ __global__ __launch_bounds__(256) void k_med_select(MedState* st, unsigned long 
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0 && pass == 2) {
+    if (threadIdx.x == 0 && pass == 2 && finish) {
         const double v1 = (double)__uint_as_float(st->prefix[0]);
         const double v2 = (double)__uint_as_float(st->prefix[1]);
         const double med = 0.5 * (sqrt(v1) + sqrt(v2));
@@ -429,6 +604,9 @@ __global__ __launch_bounds__(256) void k_svgd_merge(SvgdJob J, int R) {
 
 struct SvLayout {
     MedState* st;
+    MedState* sst;     // selection state of the bracket's sample (large T)
+    float* samp;       // [kMedSample] sampled squared distances (large T)
+    float* cand;       // [cand_cap(T)] squared distances inside the bracket (large T)
     unsigned long long* hist;
     float* score;
     float4* cmed;      // raw coordinates for the median
@@ -458,7 +636,11 @@ static SvLayout sv_layout(void* ws, int T, int d) {
     svgd_plan(T, nqb, splits, kps);
     const int Tpad = pad_keys(T);
     L.st = a.take<MedState>(1);
+    L.sst = a.take<MedState>(1);
     L.hist = a.take<unsigned long long>(2 * kMedBins);
+    const bool bracket = T >= kBracketMinT;
+    L.samp = bracket ? a.take<float>(kMedSample) : nullptr;
+    L.cand = bracket ? a.take<float>((size_t)cand_cap(T)) : nullptr;
     L.score = a.take<float>((size_t)T * d);
     L.cmed = a.take<float4>(T);
     L.qc = a.take<float4>(T);
@@ -512,15 +694,42 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
         hipLaunchKernelGGL(k_med_coords, dim3((T + 255) / 256), dim3(256), 0, st, x, T, d, L.cmed);
         CT_CHECK_HIP(hipGetLastError());
         const int nt = (T + 255) / 256;
+        const dim3 tiles(nt * nt * med_sub(nt));
+        if (T >= kBracketMinT) {
+            const unsigned long long cap = cand_cap(T);
+            hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, L.sst);
+            if (d == 2)
+                hipLaunchKernelGGL(k_med_sample<2>, dim3(kMedSample / 256), dim3(256), 0, st, L.cmed, T, L.samp);
+            else
+                hipLaunchKernelGGL(k_med_sample<3>, dim3(kMedSample / 256), dim3(256), 0, st, L.cmed, T, L.samp);
+            CT_CHECK_HIP(hipGetLastError());
+            for (int pass = 0; pass < 3; ++pass) {
+                hipLaunchKernelGGL(k_flat_hist, dim3(1024), dim3(256), 0, st, L.samp, kMedSample,
+                                   (const unsigned long long*)nullptr, 0ull, pass, L.sst, -1, L.hist);
+                hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.sst, L.hist, pass, T, -1, 0);
+                CT_CHECK_HIP(hipGetLastError());
+            }
+            if (d == 2)
+                hipLaunchKernelGGL(k_med_bracket<2>, tiles, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
+            else
+                hipLaunchKernelGGL(k_med_bracket<3>, tiles, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
+            hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(64), 0, st, L.st, T, cap);
+            CT_CHECK_HIP(hipGetLastError());
+            for (int pass = 0; pass < 3; ++pass) {
+                hipLaunchKernelGGL(k_flat_hist, dim3(1024), dim3(256), 0, st, L.cand, 0,
+                                   reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(L.st) + offsetof(MedState, ncand)), cap, pass, L.st, 1, L.hist);
+                hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.st, L.hist, pass, T, 1, 1);
+                CT_CHECK_HIP(hipGetLastError());
+            }
+        }
+        // all pairs (small T, or a bracket that missed): each kernel returns at once otherwise
         for (int pass = 0; pass < 3; ++pass) {
             if (d == 2)
-                hipLaunchKernelGGL(k_med_hist<2>, dim3(nt * nt * med_sub(nt)), dim3(256), 0, st, L.cmed,
-                                   T, pass, L.st, L.hist);
+                hipLaunchKernelGGL(k_med_hist<2>, tiles, dim3(256), 0, st, L.cmed, T, pass, L.st, L.hist);
             else
-                hipLaunchKernelGGL(k_med_hist<3>, dim3(nt * nt * med_sub(nt)), dim3(256), 0, st, L.cmed,
-                                   T, pass, L.st, L.hist);
+                hipLaunchKernelGGL(k_med_hist<3>, tiles, dim3(256), 0, st, L.cmed, T, pass, L.st, L.hist);
             CT_CHECK_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.st, L.hist, pass, T);
+            hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.st, L.hist, pass, T, 0, 1);
             CT_CHECK_HIP(hipGetLastError());
         }
     }

@@ -67,3 +67,29 @@ def test_degenerate_cases(ct):
     phi, h, sc = _gpu(ct, xc, g)
     assert h == 1.0
     np.testing.assert_allclose(phi, sc, rtol=1e-6)
+
+
+@pytest.mark.parametrize("cfg,T", [("grad_2d", 20000), ("autograd_3d", 17000)])
+def test_bracketed_median_is_exact(ct, cfg, T):
+    # large T: the median comes from a sampled bracket and one pass over all pairs;
+    # the pairs strictly below / at most the returned median must straddle the middle ranks
+    x, _y, _w, g = W.config_inputs(W.CONFIGS[cfg], T=T, M=16)
+    _phi, h, _sc = _gpu(ct, x, g)
+    med2 = h * np.log(T)
+    npair = T * (T - 1) // 2
+    lt, _ = oracle.pair_count(x, med2 * (1 - 2e-6))
+    _, le = oracle.pair_count(x, med2 * (1 + 2e-6))
+    assert lt <= npair // 2 and le >= (npair + 1) // 2, (lt, le, npair)
+
+
+def test_bracket_miss_falls_back_to_all_pairs(ct):
+    # two coincident clusters of 10000 points: squared distances are 0 (99 990 000
+    # pairs) or 0.5 (100 000 000 pairs), so the sampled bracket spans both values,
+    # its candidates overflow, and the selection reruns over all pairs.  Both middle
+    # ranks fall among the cross pairs: med^2 = 0.5.
+    T = 20000
+    x = np.full((T, 2), 0.25, np.float32)
+    x[T // 2:] = 0.75
+    g = W.gmm_params(np.random.default_rng(0), 1, 2, 0.05, 0.1)
+    _phi, h, _sc = _gpu(ct, x, g)
+    assert h == pytest.approx(0.5 / np.log(T), rel=1e-6)
