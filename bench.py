@@ -211,8 +211,10 @@ def main() -> int:
     total_pairs = sk_pairs + svgd_pairs
 
     # live per-launch timing of the dominant kernel (the lagged-shift sweep): one
-    # more step with the same launches serialised on one stream, so that each
-    # event pair brackets its kernel alone
+    # more step with the same launches serialised on one stream: each sweep kernel
+    # runs alone and carries a pair of events stamped with its own start and end
+    # (recording them inside the two-stream timed steps slows the host enqueue by
+    # about a third, so they are taken in this extra step)
     L = _lib.lib()
     L.ct_profile_clear()
     L.ct_profile_enable(1)

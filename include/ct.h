@@ -413,9 +413,12 @@ void ct_tuning_clear(void);
 /* ------------------------------------------------------------------------- */
 
 /*
- * While enabled, every sweep-kernel launch is bracketed by a pair of HIP events
- * recorded on its stream (adds two event records per launch; do not enable while
- * capturing a graph).  Record i gives (kind4 = {0 / 1 for a tracked-maximum /
+ * While enabled, every sweep kernel of ct_sinkhorn_grad (and the merge kernel
+ * after it) is launched with hipExtLaunchKernelGGL and a pair of HIP events that
+ * the runtime stamps with the kernel's own start and end on its stream; the
+ * batched and Stein launches are bracketed by event records instead.  Two events
+ * per launch (do not enable while capturing a graph; the event bookkeeping slows
+ * the host enqueue).  Record i gives (kind4 = {0 / 1 for a tracked-maximum /
  * lagged-shift sweep, or 10 / 11 for the merge kernel that follows it; offsets
  * pass 0/1; 100 * queries per lane + 10 * key-splitting waves + separate merge;
  * blocks}, the launch's point pairs (0 for a merge), its elapsed ms);

@@ -125,6 +125,11 @@ hipError_t launch_tab(int d, const Schedule& sc, bool lagged, bool bary, const T
 bool profiling();
 void* profile_begin(hipStream_t s);
 void profile_end(void* tok, hipStream_t s, int lagged, int bary, int code, int blocks, double pairs);
+// Events for one kernel launched with hipExtLaunchKernelGGL, which stamps them
+// with the kernel's own start and end (no dispatch gap): *e0, *e1 stay null when
+// profiling is off.  profile_kernel_end stores the record's description.
+void* profile_kernel_begin(hipEvent_t* e0, hipEvent_t* e1);
+void profile_kernel_end(void* tok, int lagged, int bary, int code, int blocks, double pairs);
 
 // Tuning table lookup (falls back to a size heuristic).
 Schedule schedule_for(int d, int64_t nq, int64_t nk);

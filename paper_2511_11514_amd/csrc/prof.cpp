@@ -42,6 +42,33 @@ void profile_end(void* tok, hipStream_t s, int lagged, int bary, int code, int b
     (void)hipEventRecord(r.e1, s);
 }
 
+void* profile_kernel_begin(hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (!g_on) return nullptr;
+    Rec r{};
+    if (hipEventCreate(&r.e0) != hipSuccess) return nullptr;
+    if (hipEventCreate(&r.e1) != hipSuccess) {
+        (void)hipEventDestroy(r.e0);
+        return nullptr;
+    }
+    *e0 = r.e0;
+    *e1 = r.e1;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_recs.push_back(r);
+    return reinterpret_cast<void*>(g_recs.size());
+}
+
+void profile_kernel_end(void* tok, int lagged, int bary, int code, int blocks, double pairs) {
+    if (!tok) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Rec& r = g_recs[reinterpret_cast<size_t>(tok) - 1];
+    r.kind[0] = lagged;
+    r.kind[1] = bary;
+    r.kind[2] = code;
+    r.kind[3] = blocks;
+    r.pairs = pairs;
+}
+
 }  // namespace ct
 
 using namespace ct;

@@ -1,5 +1,7 @@
 // The per-problem sweep kernel: one or two soft-min jobs per launch, each split
 // into (query block x key range) work units; see sweep_device.h.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "ct_internal.h"
@@ -91,86 +93,100 @@ size_t job_part_floats_max(int d, int nq, int nk) {
 
 size_t job_tickets_max(int nq) { return (size_t)(nq + 63) / 64; }
 
+// Launch a kernel; with profiling events, through hipExtLaunchKernelGGL so that
+// the events carry the kernel's own start and end.
+template <typename K, typename... A>
+static void launch_k(K kernel, int nb, hipStream_t s, hipEvent_t e0, hipEvent_t e1, A... args) {
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, dim3(nb), dim3(kBlock), 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, dim3(nb), dim3(kBlock), 0, s, args...);
+}
+
 template <int D, int R, int WS, bool SEP>
-static hipError_t launch_drws(bool lagged, bool bary, const Launch& L, int nb, hipStream_t s) {
+static hipError_t launch_drws(bool lagged, bool bary, const Launch& L, int nb, hipStream_t s,
+                              hipEvent_t e0, hipEvent_t e1) {
     if (lagged) {
-        if (bary)
-            hipLaunchKernelGGL((k_sweep<D, R, WS, true, true, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
-        else
-            hipLaunchKernelGGL((k_sweep<D, R, WS, true, false, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
+        if (bary) launch_k(k_sweep<D, R, WS, true, true, SEP>, nb, s, e0, e1, L);
+        else launch_k(k_sweep<D, R, WS, true, false, SEP>, nb, s, e0, e1, L);
     } else {
-        if (bary)
-            hipLaunchKernelGGL((k_sweep<D, R, WS, false, true, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
-        else
-            hipLaunchKernelGGL((k_sweep<D, R, WS, false, false, SEP>), dim3(nb), dim3(kBlock), 0, s, L);
+        if (bary) launch_k(k_sweep<D, R, WS, false, true, SEP>, nb, s, e0, e1, L);
+        else launch_k(k_sweep<D, R, WS, false, false, SEP>, nb, s, e0, e1, L);
     }
     return hipGetLastError();
 }
 
 template <int D, int R, int WS>
 static hipError_t launch_drw(bool sep, bool lagged, bool bary, const Launch& L, int nb,
-                             hipStream_t s) {
-    return sep ? launch_drws<D, R, WS, true>(lagged, bary, L, nb, s)
-               : launch_drws<D, R, WS, false>(lagged, bary, L, nb, s);
+                             hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    return sep ? launch_drws<D, R, WS, true>(lagged, bary, L, nb, s, e0, e1)
+               : launch_drws<D, R, WS, false>(lagged, bary, L, nb, s, e0, e1);
 }
 
-template <int D>
-static hipError_t launch_merge(int R, int WS, bool lagged, bool bary, const Launch& L,
-                               hipStream_t s) {
+static int merge_blocks(const Launch& L) {
     int nb = 0;
     for (int j = 0; j < L.njobs; ++j)
         if (L.job[j].splits > 1) nb += (L.job[j].nq + kMergeRows - 1) / kMergeRows;
-    if (nb == 0) return hipSuccess;
+    return nb;
+}
+
+template <int D>
+static hipError_t launch_merge(int R, int WS, bool lagged, bool bary, const Launch& L, int nb,
+                               hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (lagged) {
-        if (bary) hipLaunchKernelGGL((k_merge<D, true, true>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
-        else hipLaunchKernelGGL((k_merge<D, true, false>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
+        if (bary) launch_k(k_merge<D, true, true>, nb, s, e0, e1, L, R, WS);
+        else launch_k(k_merge<D, true, false>, nb, s, e0, e1, L, R, WS);
     } else {
-        if (bary) hipLaunchKernelGGL((k_merge<D, false, true>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
-        else hipLaunchKernelGGL((k_merge<D, false, false>), dim3(nb), dim3(kBlock), 0, s, L, R, WS);
+        if (bary) launch_k(k_merge<D, false, true>, nb, s, e0, e1, L, R, WS);
+        else launch_k(k_merge<D, false, false>, nb, s, e0, e1, L, R, WS);
     }
     return hipGetLastError();
 }
 
 template <int D, int R>
 static hipError_t launch_dr(int WS, bool sep, bool lagged, bool bary, const Launch& L, int nb,
-                            hipStream_t s) {
+                            hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     switch (WS) {
-        case 1: return launch_drw<D, R, 1>(sep, lagged, bary, L, nb, s);
-        case 2: return launch_drw<D, R, 2>(sep, lagged, bary, L, nb, s);
-        default: return launch_drw<D, R, 4>(sep, lagged, bary, L, nb, s);
+        case 1: return launch_drw<D, R, 1>(sep, lagged, bary, L, nb, s, e0, e1);
+        case 2: return launch_drw<D, R, 2>(sep, lagged, bary, L, nb, s, e0, e1);
+        default: return launch_drw<D, R, 4>(sep, lagged, bary, L, nb, s, e0, e1);
     }
 }
 
 template <int D>
 static hipError_t launch_d(const Schedule& sc, bool lagged, bool bary, const Launch& L, int nb,
-                           hipStream_t s) {
+                           hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     const bool sep = sc.sep != 0;
     switch (sc.R) {
-        case 1: return launch_dr<D, 1>(sc.WS, sep, lagged, bary, L, nb, s);
-        case 2: return launch_dr<D, 2>(sc.WS, sep, lagged, bary, L, nb, s);
-        case 4: return launch_dr<D, 4>(sc.WS, sep, lagged, bary, L, nb, s);
-        default: return launch_dr<D, 8>(sc.WS, sep, lagged, bary, L, nb, s);
+        case 1: return launch_dr<D, 1>(sc.WS, sep, lagged, bary, L, nb, s, e0, e1);
+        case 2: return launch_dr<D, 2>(sc.WS, sep, lagged, bary, L, nb, s, e0, e1);
+        case 4: return launch_dr<D, 4>(sc.WS, sep, lagged, bary, L, nb, s, e0, e1);
+        default: return launch_dr<D, 8>(sc.WS, sep, lagged, bary, L, nb, s, e0, e1);
     }
 }
 
 // One sweep: the sweep kernel, then (separate-merge schedules) the merge kernel.
-// With profiling on, each kernel gets its own event pair: kind4[0] is 0/1 for a
-// safe/lagged sweep and 10/11 for its merge.
+// With profiling on, each kernel gets its own event pair stamped with the
+// kernel's start and end: kind4[0] is 0/1 for a safe/lagged sweep and 10/11 for
+// its merge.
 hipError_t launch_sweep(int d, const Schedule& sc, bool lagged, bool bary, const Launch& L,
                         int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     double pairs = 0.0;
     for (int j = 0; j < L.njobs; ++j) pairs += (double)L.job[j].nq * L.job[j].nk;
     const int code = sc.R * 100 + sc.WS * 10 + sc.sep;
-    void* tok = profile_begin(s);
-    hipError_t e = d == 2 ? launch_d<2>(sc, lagged, bary, L, nblocks, s)
-                          : launch_d<3>(sc, lagged, bary, L, nblocks, s);
-    if (tok) profile_end(tok, s, lagged, bary, code, nblocks, pairs);
+    hipEvent_t e0, e1;
+    void* tok = profile_kernel_begin(&e0, &e1);
+    hipError_t e = d == 2 ? launch_d<2>(sc, lagged, bary, L, nblocks, s, e0, e1)
+                          : launch_d<3>(sc, lagged, bary, L, nblocks, s, e0, e1);
+    profile_kernel_end(tok, lagged, bary, code, nblocks, pairs);
     if (e != hipSuccess || !sc.sep) return e;
-    tok = profile_begin(s);
-    e = d == 2 ? launch_merge<2>(sc.R, sc.WS, lagged, bary, L, s)
-               : launch_merge<3>(sc.R, sc.WS, lagged, bary, L, s);
-    if (tok) profile_end(tok, s, 10 + lagged, bary, code, 0, 0.0);
+    const int nm = merge_blocks(L);
+    if (nm == 0) return hipSuccess;
+    tok = profile_kernel_begin(&e0, &e1);
+    e = d == 2 ? launch_merge<2>(sc.R, sc.WS, lagged, bary, L, nm, s, e0, e1)
+               : launch_merge<3>(sc.R, sc.WS, lagged, bary, L, nm, s, e0, e1);
+    profile_kernel_end(tok, 10 + lagged, bary, code, 0, 0.0);
     return e;
 }
 
