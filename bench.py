@@ -43,10 +43,16 @@ def pair_mix(d: int) -> dict:
     return {"add": d + 2.0, "fma": float(d), "exp": 1.0}
 
 
-def pair_roof(d: int, rates: dict, n_cu=N_CU, clock=CLOCK_HZ) -> float:
+def pair_roof(d: int, rates: dict, n_cu=N_CU, clock=CLOCK_HZ, mix=None) -> float:
     """Pairs per second when every CU issues the pair mix back to back."""
-    clk_per_pair = sum(n / rates[k] for k, n in pair_mix(d).items())
+    clk_per_pair = sum(n / rates[k] for k, n in (mix or pair_mix(d)).items())
     return n_cu * clock / clk_per_pair
+
+
+# The Stein flow's T x T sum (d = 2) issues per pair 2 subtractions, 1 multiply,
+# 5 FMAs and 1 v_exp_f32 (from its compiled loop); the multiply is counted at the
+# add rate, which gives the higher (stricter) peak.
+STEIN_MIX = {"add": 3.0, "fma": 5.0, "exp": 1.0}
 
 
 def sweep_source_hash() -> str:
@@ -288,6 +294,8 @@ def main() -> int:
             "frac_of_probe_peak": ach / probe_peak,
         },
     }
+    if use_svgd:
+        res["stein"] = stein_leg(ct, torch, dev, L, _lib)
     if not args.no_batched:
         res["batched"] = batched_leg(ct, torch, dev)
     if not args.no_cpu:
@@ -437,6 +445,54 @@ def grid_leg(ct, torch, dev, reps: int = 20) -> None:
                       "cpu_oracle_ms": 1e3 * t_cpu2,
                       "cpu_sample": f"{it_cpu} iterations scaled to {cfg.iters}",
                       "cpu_threads": threads}), flush=True)
+
+
+def stein_leg(ct, torch, dev, L, _lib) -> dict:
+    """The Stein flow at the large workload's size (T = 65536, 16-component mixture
+    with a 10 % floor, median bandwidth): whole-flow time, the time with the
+    bandwidth given (no median), and the T x T sum kernel against its issue roof
+    (events stamped with the kernel's start and end)."""
+    import workloads as W
+    cfg = W.CONFIGS["roofline_2d"]
+    x, _y, _w, g = W.config_inputs(cfg, M=16)
+    T = len(x)
+    xt = torch.as_tensor(x, device=dev)
+    gm = ct.GMM.from_numpy(g, dev)
+
+    def timed(h, reps=3):
+        out = ct.svgd_grad(xt, gm, h)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = ct.svgd_grad(xt, gm, h)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+
+    flow_ms, (_phi, hu) = timed(None)
+    h = float(hu.item())
+    fixed_ms, _ = timed(h)
+    L.ct_profile_clear()
+    L.ct_profile_enable(1)
+    ct.svgd_grad(xt, gm, h)
+    torch.cuda.synchronize()
+    L.ct_profile_enable(0)
+    kind = (ctypes.c_int32 * 4)()
+    pr, t = ctypes.c_double(), ctypes.c_float()
+    sum_ms = None
+    for i in range(L.ct_profile_count()):
+        _lib.check("ct_profile_read", L.ct_profile_read(i, kind, ctypes.byref(pr), ctypes.byref(t)))
+        if kind[0] == 2:
+            sum_ms = t.value
+    L.ct_profile_clear()
+    peak = pair_roof(2, NOMINAL_RATES, mix=STEIN_MIX) / 1e12
+    ach = T * T / (sum_ms * 1e-3) / 1e12 if sum_ms else None
+    return {"workload": f"roofline_2d Stein flow: T={T}, 16-component mixture + 10% floor",
+            "flow_ms": flow_ms, "flow_fixed_h_ms": fixed_ms, "median_ms": flow_ms - fixed_ms,
+            "sum_kernel": {"us": None if sum_ms is None else sum_ms * 1e3, "achieved": ach,
+                           "peak": peak, "unit": "Tpair/s",
+                           "frac": None if ach is None else ach / peak, "pair_mix": STEIN_MIX}}
 
 
 def batched_leg(ct, torch, dev) -> dict:

@@ -415,8 +415,9 @@ void ct_tuning_clear(void);
 /*
  * While enabled, every sweep kernel of ct_sinkhorn_grad (and the merge kernel
  * after it) is launched with hipExtLaunchKernelGGL and a pair of HIP events that
- * the runtime stamps with the kernel's own start and end on its stream; the
- * batched and Stein launches are bracketed by event records instead.  Two events
+ * the runtime stamps with the kernel's own start and end on its stream, as is the
+ * T x T sum of the Stein flow (kind4[0] = 2, pairs = T^2); the batched launches
+ * are bracketed by event records instead.  Two events
  * per launch (do not enable while capturing a graph; the event bookkeeping slows
  * the host enqueue).  Record i gives (kind4 = {0 / 1 for a tracked-maximum /
  * lagged-shift sweep, or 10 / 11 for the merge kernel that follows it; offsets

@@ -20,6 +20,8 @@
 //                 pre-scaled by sqrt(log2(e)/h) so k_ij = 2^-|x'_i - x'_j|^2;
 //   k_svgd_sum / k_svgd_merge   the T x T sum, split over keys like the Sinkhorn
 //                 sweep (keys read as wave-uniform records), fixed-order merge.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 #include <cstddef>
 #include <cstring>
@@ -747,12 +749,19 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
     J.st = L.st;
     J.phi = phi;
     J.h_used = h_used;
-    void* tok = profile_begin(st);
-    if (d == 2)
-        hipLaunchKernelGGL((k_svgd_sum<2, kSvR>), dim3(J.nqb * J.splits), dim3(256), 0, st, J);
-    else
-        hipLaunchKernelGGL((k_svgd_sum<3, kSvR>), dim3(J.nqb * J.splits), dim3(256), 0, st, J);
+    // with profiling on, the sum kernel carries events stamped with its own start and end
+    hipEvent_t e0, e1;
+    void* tok = profile_kernel_begin(&e0, &e1);
+    const dim3 grid(J.nqb * J.splits), block(256);
+    if (d == 2) {
+        if (e0) hipExtLaunchKernelGGL((k_svgd_sum<2, kSvR>), grid, block, 0, st, e0, e1, 0, J);
+        else hipLaunchKernelGGL((k_svgd_sum<2, kSvR>), grid, block, 0, st, J);
+    } else {
+        if (e0) hipExtLaunchKernelGGL((k_svgd_sum<3, kSvR>), grid, block, 0, st, e0, e1, 0, J);
+        else hipLaunchKernelGGL((k_svgd_sum<3, kSvR>), grid, block, 0, st, J);
+    }
     CT_CHECK_HIP(hipGetLastError());
+    profile_kernel_end(tok, 2, 0, kSvR * 100, J.nqb * J.splits, (double)T * T);
     if (d == 2)
         hipLaunchKernelGGL(k_svgd_merge<2>, dim3((T + kSvMergeRows - 1) / kSvMergeRows), dim3(256), 0,
                            st, J, kSvR);
@@ -760,7 +769,6 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
         hipLaunchKernelGGL(k_svgd_merge<3>, dim3((T + kSvMergeRows - 1) / kSvMergeRows), dim3(256), 0,
                            st, J, kSvR);
     CT_CHECK_HIP(hipGetLastError());
-    if (tok) profile_end(tok, st, 2, 0, kSvR * 100, J.nqb * J.splits, (double)T * T);
     return CT_OK;
 }
 
