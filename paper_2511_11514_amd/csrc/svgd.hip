@@ -120,7 +120,6 @@ struct MedState {
 // runs over all pairs instead (same result, three full passes).
 constexpr int kMedSample = 1 << 20;
 constexpr int kBracketMinT = 11000;
-constexpr int kCandLds = 4096;
 constexpr unsigned long long kSampleLo = 522240;   // floor((1/2 - 4 * 0.5 / 1024) * 2^20)
 constexpr unsigned long long kSampleHi = 526335;   // ceil((1/2 + 4 * 0.5 / 1024) * 2^20) - 1
 
@@ -205,20 +204,38 @@ __global__ __launch_bounds__(256) void k_med_sample(const float4* __restrict__ c
 // and flushing of the histogram when there are many tiles.
 __host__ __device__ constexpr int med_sub(int nt) { return nt * (nt + 1) / 2 < 1024 ? 4 : 1; }
 
+// Tile t of the (row tile, column tile) index space: rows bi*256.., columns
+// bj*256 + sub*jw..; false for tiles below the diagonal or past the end.
+struct MedTile {
+    int i0, j0, j1;
+};
+__device__ __forceinline__ bool med_tile(int t, int T, int nt, MedTile& mt) {
+    const int nsub = med_sub(nt), jw = 256 / nsub;
+    const int bi = t % nt, rest = t / nt;
+    const int bj = rest / nsub, sub = rest % nsub;
+    mt.i0 = bi * 256;
+    mt.j0 = bj * 256 + sub * jw;
+    mt.j1 = min(T, mt.j0 + jw);
+    return bj >= bi && mt.j0 < T;
+}
+
+// Blocks of the pair kernels below: a grid-stride loop over the tiles, so that
+// a launch whose mode does not match exits at once and each block clears and
+// flushes its histogram once.
+inline int med_grid(int T) {
+    const int nt = (T + 255) / 256;
+    return std::min(nt * nt * med_sub(nt), kNumCU * 8);
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, int T, int pass,
                                                   const MedState* __restrict__ st,
                                                   unsigned long long* __restrict__ hist) {
     __shared__ unsigned h[2][kMedBins];
     __shared__ float4 cj[256];
+    if (st->mode != 0) return;
     const int nt = (T + 255) / 256;
-    const int nsub = med_sub(nt), jw = 256 / nsub;
-    const int bi = blockIdx.x % nt;
-    const int rest = blockIdx.x / nt;
-    const int bj = rest / nsub, sub = rest % nsub;
-    const int j0 = bj * 256 + sub * jw;
-    if (bj < bi || j0 >= T || st->mode != 0) return;
-    const int j1 = min(T, j0 + jw);
+    const int ntiles = nt * nt * med_sub(nt);
     const MedPass P = med_pass(pass);
     const unsigned pa = st->prefix[0], pb = st->prefix[1];
     const bool two = pa != pb;
@@ -227,16 +244,21 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
         h[0][k] = 0u;
         h[1][k] = 0u;
     }
-    if ((int)threadIdx.x < j1 - j0) cj[threadIdx.x] = c[j0 + threadIdx.x];
-    __syncthreads();
-    const int i = bi * 256 + (int)threadIdx.x;
-    if (i < T && i < j1 - 1) {
-        const float4 xi = c[i];
-        for (int j = max(j0, i + 1); j < j1; ++j) {
-            const unsigned v = __float_as_uint(sqdist<D>(xi, cj[j - j0]));
-            const unsigned bin = (v >> P.shift) & (unsigned)(nb - 1);
-            if ((v & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
-            if (two && (v & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        MedTile mt;
+        if (!med_tile(t, T, nt, mt)) continue;
+        __syncthreads();              // the previous tile's columns are no longer read
+        if ((int)threadIdx.x < mt.j1 - mt.j0) cj[threadIdx.x] = c[mt.j0 + threadIdx.x];
+        __syncthreads();
+        const int i = mt.i0 + (int)threadIdx.x;
+        if (i < T && i < mt.j1 - 1) {
+            const float4 xi = c[i];
+            for (int j = max(mt.j0, i + 1); j < mt.j1; ++j) {
+                const unsigned v = __float_as_uint(sqdist<D>(xi, cj[j - mt.j0]));
+                const unsigned bin = (v >> P.shift) & (unsigned)(nb - 1);
+                if ((v & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
+                if (two && (v & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
+            }
         }
     }
     __syncthreads();
@@ -279,63 +301,107 @@ __global__ __launch_bounds__(256) void k_flat_hist(const float* __restrict__ v, 
 }
 
 // One pass over all pairs i < j (tiled as k_med_hist): count the pairs below the
-// bracket [lo, hi] found on the sample, collect those inside (staged in LDS,
-// one global append per block; overflow of the LDS stage appends directly).
+// bracket [lo, hi] found on the sample and collect those inside.  Each thread
+// keeps up to kCandSlots candidates of a tile in its own LDS column (plain
+// stores, no atomics in the pair loop); after the tile a block prefix sum of
+// the counts places them in the global buffer with one append per block.  A
+// thread with more than kCandSlots in one tile appends the rest directly.
+constexpr int kCandSlots = 16;
+constexpr int kBracketRows = 4;                  // rows per thread: tiles of 1024 x 256
+
+inline int bracket_grid(int T) {
+    const int ntr = (T + 256 * kBracketRows - 1) / (256 * kBracketRows), ntc = (T + 255) / 256;
+    return std::min(ntr * ntc, kNumCU * 8);
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ c, int T,
                                                      const MedState* __restrict__ sst,
                                                      MedState* st, float* __restrict__ cand,
                                                      unsigned long long cap) {
+    constexpr int RB = kBracketRows;
     __shared__ float4 cj[256];
-    __shared__ float lc[kCandLds];
-    __shared__ unsigned ln;
-    __shared__ unsigned red[256];
+    __shared__ float slots[kCandSlots][256];
+    __shared__ unsigned wsum[4];
     __shared__ unsigned long long base;
-    const int nt = (T + 255) / 256;
-    const int nsub = med_sub(nt), jw = 256 / nsub;
-    const int bi = blockIdx.x % nt;
-    const int rest = blockIdx.x / nt;
-    const int bj = rest / nsub, sub = rest % nsub;
-    const int j0 = bj * 256 + sub * jw;
-    if (bj < bi || j0 >= T) return;
-    const int j1 = min(T, j0 + jw);
+    const int ntr = (T + 256 * RB - 1) / (256 * RB), ntc = (T + 255) / 256;
+    const int ntiles = ntr * ntc;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
     const unsigned lo = sst->prefix[0], hi = sst->prefix[1];
-    if (threadIdx.x == 0) ln = 0u;
-    if ((int)threadIdx.x < j1 - j0) cj[threadIdx.x] = c[j0 + threadIdx.x];
-    __syncthreads();
-    unsigned below = 0u;
-    const int i = bi * 256 + (int)threadIdx.x;
-    if (i < T && i < j1 - 1) {
-        const float4 xi = c[i];
-        for (int j = max(j0, i + 1); j < j1; ++j) {
-            const float d2 = sqdist<D>(xi, cj[j - j0]);
-            const unsigned u = __float_as_uint(d2);
-            below += u < lo ? 1u : 0u;
-            if (u >= lo && u <= hi) {
-                const unsigned k = atomicAdd(&ln, 1u);
-                if (k < (unsigned)kCandLds) {
-                    lc[k] = d2;
-                } else {
-                    const unsigned long long g = atomicAdd(&st->ncand, 1ull);
-                    if (g < cap) cand[g] = d2;
+    const unsigned span = hi - lo;                 // u in [lo, hi]  <=>  u - lo <= span
+    unsigned long long below = 0ull;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int i0 = (t % ntr) * 256 * RB;
+        const int j0 = (t / ntr) * 256;
+        const int j1 = min(T, j0 + 256);
+        if (j1 - 1 <= i0) continue;               // no column j > any row i of the tile
+        __syncthreads();                           // previous tile: columns and slots consumed
+        if ((int)threadIdx.x < j1 - j0) cj[threadIdx.x] = c[j0 + threadIdx.x];
+        __syncthreads();
+        float4 xi[RB];
+        int ir[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            ir[r] = i0 + r * 256 + (int)threadIdx.x;
+            // rows past the end take j > T, which no column satisfies
+            xi[r] = ir[r] < T ? c[ir[r]] : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ir[r] >= T) ir[r] = T;
+        }
+        unsigned nin = 0u, bl = 0u;
+        const int n = j1 - j0;
+        for (int jj = 0; jj < n; jj += 8) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const int jl = jj + g;
+                if (jl < n) {
+                    const float4 xj = cj[jl];
+                    const int j = j0 + jl;
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        const float d2 = sqdist<D>(xi[r], xj);
+                        const unsigned u = __float_as_uint(d2);
+                        const bool ok = j > ir[r];
+                        bl += (ok && u < lo) ? 1u : 0u;
+                        if (ok && u - lo <= span) {
+                            if (nin < (unsigned)kCandSlots) {
+                                slots[nin][threadIdx.x] = d2;
+                            } else {
+                                const unsigned long long gi = atomicAdd(&st->ncand, 1ull);
+                                if (gi < cap) cand[gi] = d2;
+                            }
+                            ++nin;
+                        }
+                    }
                 }
             }
         }
-    }
-    red[threadIdx.x] = below;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        below += bl;
+        // block exclusive prefix sum of the kept counts
+        const unsigned kept = min(nin, (unsigned)kCandSlots);
+        unsigned inc = kept;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        if (lane == 63) wsum[wave] = inc;
         __syncthreads();
+        unsigned before = 0u, total = 0u;
+        for (int w = 0; w < 4; ++w) {
+            before += w < wave ? wsum[w] : 0u;
+            total += wsum[w];
+        }
+        if (threadIdx.x == 0) base = total ? atomicAdd(&st->ncand, (unsigned long long)total) : 0ull;
+        __syncthreads();
+        const unsigned long long off = base + before + inc - kept;
+        for (unsigned k = 0; k < kept; ++k)
+            if (off + k < cap) cand[off + k] = slots[k][threadIdx.x];
     }
-    const unsigned n = min(ln, (unsigned)kCandLds);
-    if (threadIdx.x == 0) {
-        if (red[0]) atomicAdd(&st->below, (unsigned long long)red[0]);
-        base = n ? atomicAdd(&st->ncand, (unsigned long long)n) : 0ull;
-    }
-    __syncthreads();
-    for (unsigned k = threadIdx.x; k < n; k += 256)
-        if (base + k < cap) cand[base + k] = lc[k];
+    // pairs below the bracket: a wave sum, then one atomic per wave
+    unsigned long long b = below;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b += __shfl_down(b, o, 64);
+    if (lane == 0 && b) atomicAdd(&st->below, b);
 }
 
 // Use the candidates if both targets fall inside the bracket and none was lost.
@@ -695,8 +761,7 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
     if (h <= 0.f && T > 1) {
         hipLaunchKernelGGL(k_med_coords, dim3((T + 255) / 256), dim3(256), 0, st, x, T, d, L.cmed);
         CT_CHECK_HIP(hipGetLastError());
-        const int nt = (T + 255) / 256;
-        const dim3 tiles(nt * nt * med_sub(nt));
+        const dim3 tiles(med_grid(T));
         if (T >= kBracketMinT) {
             const unsigned long long cap = cand_cap(T);
             hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, L.sst);
@@ -711,10 +776,11 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
                 hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.sst, L.hist, pass, T, -1, 0);
                 CT_CHECK_HIP(hipGetLastError());
             }
+            const dim3 bgrid(bracket_grid(T));
             if (d == 2)
-                hipLaunchKernelGGL(k_med_bracket<2>, tiles, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
+                hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
             else
-                hipLaunchKernelGGL(k_med_bracket<3>, tiles, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
+                hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
             hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(64), 0, st, L.st, T, cap);
             CT_CHECK_HIP(hipGetLastError());
             for (int pass = 0; pass < 3; ++pass) {
