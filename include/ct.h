@@ -188,9 +188,9 @@ typedef struct ct_gmm {
     float floor;          /* uniform mass in [0, 1) */
 } ct_gmm;
 
-/* Workspace of ct_svgd_grad / ct_svgd_grad_score: O(T) bytes, plus, from T = 11000 on (median
- * bandwidth over a sampled bracket), 4 MiB of samples and 4 bytes per 125 pairs for the bracket's
- * candidates (about 69 MB at T = 65536). */
+/* Workspace of ct_svgd_grad / ct_svgd_grad_score: O(T) bytes, plus, for 11000 <= T <= 92681
+ * (median bandwidth over a sampled bracket), 4 MiB of samples and 4 bytes per 125 pairs for the
+ * bracket's candidates (about 69 MB at T = 65536). */
 size_t ct_svgd_workspace_size(int64_t T, int32_t d);
 
 /*

@@ -120,6 +120,7 @@ struct MedState {
 // runs over all pairs instead (same result, three full passes).
 constexpr int kMedSample = 1 << 20;
 constexpr int kBracketMinT = 11000;
+constexpr int kMaxMedianT = 92681;               // T(T-1)/2 pairs fit the selection's counters
 constexpr unsigned long long kSampleLo = 522240;   // floor((1/2 - 4 * 0.5 / 1024) * 2^20)
 constexpr unsigned long long kSampleHi = 526335;   // ceil((1/2 + 4 * 0.5 / 1024) * 2^20) - 1
 
@@ -706,7 +707,8 @@ static SvLayout sv_layout(void* ws, int T, int d) {
     L.st = a.take<MedState>(1);
     L.sst = a.take<MedState>(1);
     L.hist = a.take<unsigned long long>(2 * kMedBins);
-    const bool bracket = T >= kBracketMinT;
+    // the bracket's buffers exist only where a median can be asked for
+    const bool bracket = T >= kBracketMinT && T <= kMaxMedianT;
     L.samp = bracket ? a.take<float>(kMedSample) : nullptr;
     L.cand = bracket ? a.take<float>((size_t)cand_cap(T)) : nullptr;
     L.score = a.take<float>((size_t)T * d);
@@ -745,7 +747,7 @@ ct_status svgd_check(const float* x, int64_t T64, int32_t d, float h, float* phi
     if (T64 < 1 || T64 > (int64_t(1) << 30)) return fail(CT_E_SHAPE, "T must be in [1, 2^30]");
     if (!x || !phi) return fail(CT_E_ARG, "x and phi must be non-null");
     if (!std::isfinite(h)) return fail(CT_E_ARG, "h must be finite");
-    if (h <= 0.f && T64 > 92681) return fail(CT_E_SHAPE, "median bandwidth supports T <= 92681");
+    if (h <= 0.f && T64 > kMaxMedianT) return fail(CT_E_SHAPE, "median bandwidth supports T <= %d", kMaxMedianT);
     if (!ws) return fail(CT_E_ARG, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
     L = sv_layout(ws, (int)T64, d);
