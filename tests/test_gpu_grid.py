@@ -164,3 +164,20 @@ def test_planner_step_toward_a_grid_matches_oracle(ct):
                                                  step=0.05, grid=_oracle_grid(u, lo, hi, fl))
     assert abs(hist[0] - r_obj) / abs(r_obj) < 1e-5
     assert rel(u1 - u0, r_u1 - u0) < 1e-5
+
+
+def test_planner_step_toward_a_3d_grid_matches_oracle(ct):
+    # the 3-D point mass (the aircraft's stand-in) steered by the Stein flow toward a 3-D map
+    T = 400
+    rng = np.random.default_rng(77)
+    u0 = rng.normal(size=(T, 3)) * 0.1
+    s0 = np.array([0.5, 0.5, 0.5, 0.0, 0.0, 0.0])
+    Q, R = np.eye(3), 0.01 * np.eye(3)
+    u, lo, hi, fl = _maps((20, 16, 12), 93, 0.02)
+    u1, _s, hist = ct.plan("double_integrator", s0, u0, 0.05, Q, R, "svgd_grid", 1, 0.05,
+                           grid=_gpu_grid(ct, u, lo, hi, fl))
+    r_u1, _rs, r_obj, _ra, _rv = oracle.plan_step("double_integrator", s0, u0, 0.05, Q, R,
+                                                 "svgd_grid", step=0.05,
+                                                 grid=_oracle_grid(u, lo, hi, fl))
+    assert abs(hist[0] - r_obj) / abs(r_obj) < 1e-5
+    assert rel(u1 - u0, r_u1 - u0) < 1e-5
