@@ -3,6 +3,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "ct_internal.h"
@@ -429,6 +431,32 @@ void ensemble_offsets(int32_t S, int64_t T, int64_t M, std::vector<int64_t>& To,
     }
 }
 
+// Run f(b, worker) for the seeds b = 0..S-1 on up to 16 host threads (the seeds
+// are independent; each worker owns its scratch).  The first failing seed's
+// status and message (kept per thread by fail()) are passed to the caller.
+template <typename F>
+ct_status for_each_seed(int32_t S, int workers, F&& f) {
+    std::vector<ct_status> rc((size_t)S, CT_OK);
+    std::vector<std::string> msg((size_t)S);
+    auto work = [&](int wk) {
+        for (int32_t b = wk; b < S; b += workers) {
+            rc[b] = f(b, wk);
+            if (rc[b] != CT_OK) msg[b] = ct_last_error();
+        }
+    };
+    if (workers <= 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        th.reserve((size_t)workers);
+        for (int wk = 0; wk < workers; ++wk) th.emplace_back(work, wk);
+        for (auto& t : th) t.join();
+    }
+    for (int32_t b = 0; b < S; ++b)
+        if (rc[b] != CT_OK) return fail(rc[b], "seed %d: %s", b, msg[b].c_str());
+    return CT_OK;
+}
+
 EnsembleLayout ensemble_layout(void* ws, const ct_plan_problem* p, const ct_plan_opts* o,
                                int32_t S, int64_t M, bool weighted) {
     Arena a(ws);
@@ -501,18 +529,33 @@ extern "C" ct_status ct_plan_ensemble(const ct_plan_problem* p, const ct_plan_op
     so.flags &= (uint32_t)(CT_DEBIAS | CT_SAFE_LSE);
     rc = ct_sinkhorn_batched_prepare(S, To.data(), Mo.data(), &so, L.inner, L.inner_bytes, stream);
     if (rc) return rc;
-    std::vector<double> traj((size_t)(T + 1) * n), A((size_t)T * n * n), B((size_t)T * n * m);
-    std::vector<double> tgt((size_t)T * n, 0.0), v((size_t)T * m), Qn((size_t)n * n, 0.0);
+    const int workers = (int)std::max<int32_t>(
+        1, std::min<int32_t>(S, (int32_t)std::min(16u, std::max(1u, std::thread::hardware_concurrency()))));
+    struct Scratch {
+        std::vector<double> traj, A, B, tgt, v;
+    };
+    std::vector<Scratch> sc((size_t)workers);
+    for (auto& w_ : sc) {
+        w_.traj.resize((size_t)(T + 1) * n);
+        w_.A.resize((size_t)T * n * n);
+        w_.B.resize((size_t)T * n * m);
+        w_.tgt.assign((size_t)T * n, 0.0);
+        w_.v.resize((size_t)T * m);
+    }
+    std::vector<double> Qn((size_t)n * n, 0.0);
     std::vector<float> xh((size_t)S * T * d), gh((size_t)S * T * d);
     for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) Qn[i * n + j] = o->Q[i * d + j];
     auto stage_positions = [&]() -> ct_status {
-        for (int32_t b = 0; b < S; ++b) {
+        rc = for_each_seed(S, workers, [&](int32_t b, int wk) -> ct_status {
+            std::vector<double>& traj = sc[wk].traj;
             rollout(p->dynamics, D, p->s0, u + (size_t)b * T * m, T, p->dt, traj.data());
             for (int64_t t = 0; t < T; ++t)
                 for (int k = 0; k < d; ++k)
                     xh[((size_t)b * T + t) * d + k] = (float)traj[(t + 1) * n + k];
-        }
+            return CT_OK;
+        });
+        if (rc) return rc;
         CT_CHECK_HIP(hipMemcpyAsync(L.x, xh.data(), sizeof(float) * S * T * d,
                                     hipMemcpyHostToDevice, st));
         return CT_OK;
@@ -528,20 +571,24 @@ extern "C" ct_status ct_plan_ensemble(const ct_plan_problem* p, const ct_plan_op
         CT_CHECK_HIP(hipMemcpyAsync(gh.data(), L.gx, sizeof(float) * S * T * d,
                                     hipMemcpyDeviceToHost, st));
         CT_CHECK_HIP(hipStreamSynchronize(st));
-        for (int32_t b = 0; b < S; ++b) {
+        // every seed's LQR step on the host, seeds spread over threads
+        rc = for_each_seed(S, workers, [&](int32_t b, int wk) -> ct_status {
+            Scratch& w_ = sc[wk];
             double* ub = u + (size_t)b * T * m;
-            rollout(p->dynamics, D, p->s0, ub, T, p->dt, traj.data());
+            rollout(p->dynamics, D, p->s0, ub, T, p->dt, w_.traj.data());
             for (int64_t t = 0; t < T; ++t)
                 for (int k = 0; k < d; ++k)
-                    tgt[t * n + k] = -(double)T * (double)gh[((size_t)b * T + t) * d + k];
+                    w_.tgt[t * n + k] = -(double)T * (double)gh[((size_t)b * T + t) * d + k];
             for (int64_t t = 0; t < T; ++t)
-                dyn_jac(p->dynamics, D, traj.data() + t * n, ub + t * m,
-                        A.data() + (size_t)t * n * n, B.data() + (size_t)t * n * m);
-            rc = lqr_solve(T, n, m, p->dt, A.data(), B.data(), tgt.data(), Qn.data(), o->R,
-                           v.data(), nullptr);
-            if (rc) return rc;
-            for (size_t i = 0; i < v.size(); ++i) ub[i] += o->step * v[i];
-        }
+                dyn_jac(p->dynamics, D, w_.traj.data() + t * n, ub + t * m,
+                        w_.A.data() + (size_t)t * n * n, w_.B.data() + (size_t)t * n * m);
+            const ct_status r = lqr_solve(T, n, m, p->dt, w_.A.data(), w_.B.data(), w_.tgt.data(),
+                                          Qn.data(), o->R, w_.v.data(), nullptr);
+            if (r) return r;
+            for (size_t i = 0; i < w_.v.size(); ++i) ub[i] += o->step * w_.v[i];
+            return CT_OK;
+        });
+        if (rc) return rc;
     }
     // rank the final trajectories by their divergence to the reference
     rc = stage_positions();
