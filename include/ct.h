@@ -356,7 +356,8 @@ ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, const float* 
  * start from their own controls, in lockstep: every outer iteration rolls out
  * all seeds on the host, evaluates their S Sinkhorn flows in one persistent
  * launch (ct_sinkhorn_grad_batched, gradient only) and solves the S LQR problems
- * on the host, exactly as S independent ct_plan calls would.  After the last
+ * on the host (spread over up to 16 threads; each seed's result does not depend
+ * on the thread), exactly as S independent ct_plan calls would.  After the last
  * iteration the divergence of every final trajectory to the reference is
  * evaluated in one more batched launch, and the seed with the smallest is
  * reported.
