@@ -294,6 +294,7 @@ def main() -> int:
             "frac_of_probe_peak": ach / probe_peak,
         },
     }
+    res["autograd_3d"] = autograd_3d_leg(ct, torch, dev)
     if use_svgd:
         res["stein"] = stein_leg(ct, torch, dev, L, _lib)
     if not args.no_batched:
@@ -445,6 +446,43 @@ def grid_leg(ct, torch, dev, reps: int = 20) -> None:
                       "cpu_oracle_ms": 1e3 * t_cpu2,
                       "cpu_sample": f"{it_cpu} iterations scaled to {cfg.iters}",
                       "cpu_threads": threads}), flush=True)
+
+
+def autograd_3d_leg(ct, torch, dev, reps: int = 2) -> dict:
+    """The autograd form at its 3-D workload (T = 16384 random-walk samples, M = 65536
+    samples of an anisotropic 8-component mixture, eps = 0.01, K = 300): S with
+    dS/dx and dS/dw through torch.autograd, whole-pass time and pair throughput
+    against the 3-D issue roof."""
+    import workloads as W
+    cfg = W.CONFIGS["autograd_3d"]
+    x, y, w, _g = W.config_inputs(cfg)
+    T, M, K = len(x), len(y), cfg.iters
+    xt, yt, wt = (torch.as_tensor(a, device=dev) for a in (x, y, w))
+
+    def step():
+        xr = xt.detach().requires_grad_(True)
+        wr = wt.detach().requires_grad_(True)
+        S = ct.sinkhorn_divergence(xr, yt, wr, eps=cfg.eps, iters=K)
+        S.backward()
+        return xr.grad
+
+    step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g = step()
+    e1.record()
+    torch.cuda.synchronize()
+    assert torch.isfinite(g).all().item()
+    ms = e0.elapsed_time(e1) / reps
+    pairs = pairs_per_pass(T, M, K)
+    peak = pair_roof(3, NOMINAL_RATES) / 1e12
+    rate = pairs / (ms * 1e-3) / 1e12
+    return {"workload": f"autograd_3d: d=3 T={T} M={M} eps={cfg.eps} K={K}, S + dS/dx + dS/dw "
+                        "through autograd", "ms_per_pass": ms, "pairs_per_pass": pairs,
+            "pair_evals_per_s": rate * 1e12, "peak": peak, "unit": "Tpair/s",
+            "frac_of_peak": rate / peak}
 
 
 def stein_leg(ct, torch, dev, L, _lib) -> dict:
