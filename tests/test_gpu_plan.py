@@ -153,3 +153,19 @@ def test_plan_ensemble_equals_independent_plans(ct):
         assert rel(U[b] - U0[b], ub - U0[b]) < 1e-4, b
     assert np.all(np.isfinite(values)) and 0 <= best < S
     assert values[best] == values.min()
+
+
+def test_plan_ensemble_is_deterministic(ct):
+    """The seeds' host work runs on several threads; two identical calls return
+    bit-identical controls, divergences and best seed."""
+    S, T, outer = 6, 250, 3
+    c, s0, U0, y, w, Q, R = _ensemble_inputs(S, T)
+    dev = torch.device("cuda")
+    yt, wt = torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev)
+    runs = [ct.plan_ensemble(c["dynamics"], s0, U0, c["dt"], Q, R, outer, c["step"], y=yt, w=wt,
+                             eps=c["eps"], iters=c["iters"]) for _ in range(2)]
+    (U1, s1, v1, b1), (U2, s2, v2, b2) = runs
+    np.testing.assert_array_equal(U1, U2)
+    np.testing.assert_array_equal(s1, s2)
+    np.testing.assert_array_equal(v1, v2)
+    assert b1 == b2
