@@ -181,3 +181,29 @@ def test_planner_step_toward_a_3d_grid_matches_oracle(ct):
                                                  grid=_oracle_grid(u, lo, hi, fl))
     assert abs(hist[0] - r_obj) / abs(r_obj) < 1e-5
     assert rel(u1 - u0, r_u1 - u0) < 1e-5
+
+
+@pytest.mark.parametrize("n,floor", [((2, 2), 0.0), ((2, 2, 2), 1e-6), ((3, 2), 5.0)])
+def test_grid_score_single_cells_and_box_faces(ct, n, floor):
+    # the smallest grids (one cell per axis), points on every corner and face of the
+    # box and just outside it, a vanishing and a dominant floor
+    d = len(n)
+    u, lo, hi, fl = _maps(n, 300 + d, floor)
+    lo64, hi64 = lo.astype(np.float64), hi.astype(np.float64)
+    corners = np.array([[lo64[t] if (k >> t) & 1 == 0 else hi64[t] for t in range(d)]
+                        for k in range(1 << d)])
+    mids = (lo64 + hi64) / 2
+    faces = np.concatenate([np.where(np.eye(d, dtype=bool)[t], lo64, mids)[None] for t in range(d)] +
+                           [np.where(np.eye(d, dtype=bool)[t], hi64, mids)[None] for t in range(d)])
+    eps = (hi64 - lo64) * 1e-3
+    outside = np.concatenate([corners - eps, corners + eps])
+    inner = np.random.default_rng(d).uniform(lo64, hi64, (200, d))
+    x = np.concatenate([corners, faces, outside, inner]).astype(np.float32)
+    sc = ct.grid_score(torch.as_tensor(x, device="cuda"), _gpu_grid(ct, u, lo, hi, fl))
+    torch.cuda.synchronize()
+    want = oracle.grid.score(_oracle_grid(u, lo, hi, fl), x.astype(np.float64))
+    np.testing.assert_allclose(sc.cpu().numpy(), want, rtol=2e-6, atol=1e-9 * max(1.0, np.abs(want).max()))
+    y, w = ct.grid_samples(_gpu_grid(ct, u, lo, hi, fl))
+    ry, rw = oracle.grid.samples(_oracle_grid(u, lo, hi, fl))
+    np.testing.assert_array_equal(y.cpu().numpy(), ry.astype(np.float32))
+    np.testing.assert_allclose(w.cpu().numpy(), rw, rtol=1e-6)
