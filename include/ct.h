@@ -9,8 +9,10 @@
  *   ct_sinkhorn_grad          gradient of the debiased Sinkhorn divergence
  *                             (Sec. II-B, eqs. 5-7) w.r.t. the trajectory samples
  *                             and the reference weights, and its value;
+ *   ct_status_sync            device-detected conditions of the last gradient call
+ *                             (non-finite inputs, rescued rows);
  *   ct_sinkhorn_grad_batched  the same for many independent problems of uneven
- *                             size in one persistent launch;
+ *                             size (lockstep launches or one persistent kernel);
  *   ct_svgd_grad              Stein variational flow (Sec. II-B, eq. 4) with an
  *                             RBF kernel and an analytic Gaussian-mixture score;
  *   ct_svgd_grad_score        the same flow for any score in device memory;
@@ -60,6 +62,7 @@ typedef int32_t ct_status;
 #define CT_E_WORKSPACE (-4)   /* ws too small or misaligned */
 #define CT_E_HIP (-5)         /* a HIP runtime call failed (message has the HIP error) */
 #define CT_E_UNSUPPORTED (-6) /* feature not available for this input */
+#define CT_W_NONFINITE 1       /* ct_status_sync: the device saw non-finite inputs or non-positive weights */
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* ct_last_error(void);
@@ -138,6 +141,20 @@ ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const floa
                            const ct_sinkhorn_opts* o, float* grad_x, float* grad_w, float* value,
                            float* pot, float* pot_plus, float* aux, void* ws, size_t ws_bytes,
                            void* stream);
+
+/*
+ * Status words that the last ct_sinkhorn_grad call on `ws` left in its workspace,
+ * read after waiting for `stream` (the one synchronising query of the Sinkhorn
+ * path; ct_sinkhorn_grad itself never waits).
+ *   ws         device, a workspace last used by ct_sinkhorn_grad (256-byte aligned)
+ *   nonfinite  host [1] or NULL  out: non-finite input coordinates plus non-positive
+ *              or non-finite weights (the count that aux[5] reports)
+ *   rescued    host [1] or NULL  out: rows whose lagged shift was unusable and that
+ *              were recomputed with a tracked maximum (aux[4])
+ * Returns CT_W_NONFINITE (positive) when nonfinite > 0, else CT_OK; CT_E_ARG for a
+ * null ws, CT_E_WORKSPACE for a misaligned one, CT_E_HIP.
+ */
+ct_status ct_status_sync(const void* ws, uint32_t* nonfinite, uint32_t* rescued, void* stream);
 
 /*
  * Many independent problems b = 0..B-1 of uneven size (the batched form of

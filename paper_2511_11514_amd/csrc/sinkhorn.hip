@@ -758,3 +758,22 @@ extern "C" ct_status ct_autotune_sinkhorn(int64_t T64, int64_t M64, const ct_sin
     CT_CHECK_HIP(hipEventDestroy(e1));
     return CT_OK;
 }
+
+extern "C" ct_status ct_status_sync(const void* ws, uint32_t* nonfinite, uint32_t* rescued,
+                                    void* stream) {
+    clear_error();
+    if (!ws) return fail(CT_E_ARG, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
+    // the counters come before every size-dependent buffer of the layout; a stand-in
+    // base (never dereferenced) gives their offset
+    char* const probe = reinterpret_cast<char*>(uintptr_t(1) << 20);
+    const size_t off = static_cast<size_t>(reinterpret_cast<char*>(sk_layout(probe, 1, 1, 2).counters) - probe);
+    unsigned c[2] = {0u, 0u};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    CT_CHECK_HIP(hipMemcpyAsync(c, static_cast<const char*>(ws) + off, sizeof(c),
+                                hipMemcpyDeviceToHost, st));
+    CT_CHECK_HIP(hipStreamSynchronize(st));
+    if (nonfinite) *nonfinite = c[0];
+    if (rescued) *rescued = c[1];
+    return c[0] ? CT_W_NONFINITE : CT_OK;
+}

@@ -217,3 +217,10 @@ def test_svgd_score_and_grid_plan_reject_bad_arguments_before_launch():
     assert "grid" in L.ct_last_error().decode()
     assert L.ct_plan_workspace_size(ctypes.byref(prob), ctypes.byref(o), 0) > \
         L.ct_svgd_workspace_size(10, 2)
+
+
+def test_status_sync_rejects_bad_workspaces():
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    assert L.ct_status_sync(None, None, None, None) == _lib.CT_E_ARG
+    assert L.ct_status_sync(ctypes.c_void_p(257), None, None, None) == _lib.CT_E_WORKSPACE

@@ -211,3 +211,41 @@ def test_one_stream_and_two_streams_agree(ct):
         assert torch.equal(a, b)
     r = _oracle(x, y, w, 0.01, 30)
     assert rel(outs[0][0].numpy(), r.grad_x) < TOL
+
+
+def test_status_sync_reports_device_detected_conditions(ct):
+    """ct_status_sync reads the workspace's status words: OK and the rescued-row
+    count for clean inputs; CT_W_NONFINITE and the count for NaN coordinates and a
+    zero weight, matching aux[5]."""
+    from paper_2511_11514_amd import _lib
+    import ctypes
+    L = _lib.lib()
+    x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=700, M=900)
+    dev = torch.device("cuda")
+    T, M, d = 700, 900, 2
+    o = _lib.SinkhornOpts(d, 20, 0.01, _lib.CT_DEBIAS | _lib.CT_VALUE)
+    nb = L.ct_sinkhorn_workspace_size(T, M, ctypes.byref(o))
+    ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+    P = lambda z: ctypes.c_void_p(z.data_ptr())
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for bad in (False, True):
+        xb, wb = x.copy(), w.copy()
+        if bad:
+            xb[3, 0] = np.nan
+            xb[10, 1] = np.nan
+            wb[5] = 0.0
+        xt, yt, wt = (torch.as_tensor(a, device=dev) for a in (xb, y, wb))
+        gx = torch.empty(T, d, device=dev)
+        val = torch.empty(1, device=dev)
+        aux = torch.empty(8, device=dev)
+        st = L.ct_sinkhorn_grad(P(xt), T, P(yt), P(wt), M, ctypes.byref(o), P(gx), None, P(val),
+                                None, None, P(aux), P(ws), nb, stream)
+        assert st == 0
+        nf, rs = ctypes.c_uint32(), ctypes.c_uint32()
+        s = L.ct_status_sync(P(ws), ctypes.byref(nf), ctypes.byref(rs), stream)
+        a = aux.cpu().numpy()
+        assert nf.value == int(a[5]) and rs.value == int(a[4])
+        if bad:
+            assert s == _lib.CT_W_NONFINITE and nf.value == 3
+        else:
+            assert s == _lib.CT_OK and nf.value == 0
