@@ -249,3 +249,18 @@ def test_status_sync_reports_device_detected_conditions(ct):
             assert s == _lib.CT_W_NONFINITE and nf.value == 3
         else:
             assert s == _lib.CT_OK and nf.value == 0
+
+
+@pytest.mark.parametrize("d,T,M", [(2, 3000, 5000), (3, 1500, 2600)])
+def test_repeated_calls_are_bitwise_identical(ct, d, T, M):
+    """Fixed-order reductions and no float atomics: two calls with the same inputs
+    and schedules return the same bits (gradients, value, potentials)."""
+    cfg = W.CONFIGS["grad_2d" if d == 2 else "autograd_3d"]
+    x, y, w, _g = W.config_inputs(cfg, T=T, M=M)
+    dev = torch.device("cuda")
+    t = lambda a: torch.as_tensor(a, device=dev)
+    outs = [ct.sinkhorn_grad(t(x), t(y), t(w), eps=cfg.eps, iters=40, value=True, grad_w=True,
+                             potentials=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    for name in ("grad_x", "grad_w", "value", "pot", "pot_plus"):
+        assert torch.equal(getattr(outs[0], name), getattr(outs[1], name)), name
