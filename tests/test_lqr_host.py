@@ -16,7 +16,7 @@ def _problem(rng, T, n, m):
     return A, B, a, Q, R
 
 
-@pytest.mark.parametrize("T,n,m", [(1, 1, 1), (9, 3, 2), (60, 4, 2), (33, 8, 8)])
+@pytest.mark.parametrize("T,n,m", [(1, 1, 1), (9, 3, 2), (60, 4, 2), (41, 6, 3), (33, 8, 8), (17, 5, 1)])
 def test_lqr_matches_oracle(ct, T, n, m):
     rng = np.random.default_rng(T * 10 + n)
     A, B, a, Q, R = _problem(rng, T, n, m)
