@@ -294,6 +294,8 @@ def main() -> int:
             "frac_of_probe_peak": ach / probe_peak,
         },
     }
+    res["parity"] = parity_vs_stored_oracle(out, ct, torch, dev)
+    res["system"] = system_info(torch, dev)
     res["autograd_3d"] = autograd_3d_leg(ct, torch, dev)
     if use_svgd:
         res["stein"] = stein_leg(ct, torch, dev, L, _lib)
@@ -446,6 +448,48 @@ def grid_leg(ct, torch, dev, reps: int = 20) -> None:
                       "cpu_oracle_ms": 1e3 * t_cpu2,
                       "cpu_sample": f"{it_cpu} iterations scaled to {cfg.iters}",
                       "cpu_threads": threads}), flush=True)
+
+
+def parity_vs_stored_oracle(out, ct, torch, dev) -> dict:
+    """Norm-wise relative errors of the timed step's last outputs against the FP64
+    oracle's pass over the same inputs, stored in tests/golden (written by the
+    fixture script from the oracle only).  The stored Stein flow was taken on the
+    workload's samples drawn beside a 16-point reference, so it is checked with one
+    more call on those inputs."""
+    import workloads as W
+    import numpy as np
+    res = {"tolerance": 1e-5, "reference": "FP64 oracle, tests/golden/grad_2d_full*.npz"}
+
+    def rel(a, b):
+        a = np.asarray(a, np.float64).ravel()
+        b = np.asarray(b, np.float64).ravel()
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+    gold = os.path.join(ROOT, "tests", "golden")
+    F = np.load(os.path.join(gold, "grad_2d_full.npz"))
+    res["value"] = abs(float(out[0].item()) - float(F["value"])) / abs(float(F["value"]))
+    res["grad_x"] = rel(out[1].cpu().numpy(), F["grad_x"])
+    res["grad_w"] = rel(out[2].cpu().numpy(), F["grad_w"])
+    if len(out) > 3:
+        G = np.load(os.path.join(gold, "grad_2d_full_svgd.npz"))
+        x, _y, _w, g = W.config_inputs(W.CONFIGS[str(G["workload"])], T=int(G["T"]), M=16)
+        phi, _h = ct.svgd_grad(torch.as_tensor(x, device=dev), ct.GMM.from_numpy(g, dev))
+        res["stein_phi"] = rel(phi.cpu().numpy(), G["phi"])
+    return res
+
+
+def system_info(torch, dev) -> dict:
+    cpu = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"gpu": torch.cuda.get_device_name(dev), "host_cpu": cpu,
+            "host_threads": os.cpu_count()}
 
 
 def autograd_3d_leg(ct, torch, dev, reps: int = 2) -> dict:
