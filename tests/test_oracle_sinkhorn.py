@@ -183,6 +183,39 @@ def test_invariances():
     np.testing.assert_allclose(r3.grad_w, r.grad_w / 3.0, atol=1e-13)
 
 
+def _dual(f, g, a, b, C, eps):
+    """Entropic dual objective of eq. 5 (relative entropy to a x b) at any pair
+    (f, g): <a,f> + <b,g> - eps sum_ij a_i b_j (exp((f_i + g_j - C_ij)/eps) - 1)."""
+    E = np.exp((f[:, None] + g[None, :] - C) / eps)
+    return a @ f + b @ g - eps * (a @ E @ b - 1.0)
+
+
+@pytest.mark.parametrize("iters", [1, 3, 8])
+def test_value_terms_are_dual_objectives_before_convergence(iters):
+    """Away from convergence each OT term of the value is the full dual objective
+    at the pair it is read from (the exponential term vanishes because the first
+    potential is row-exact for the second), and by weak duality it stays below
+    the converged term."""
+    rng = np.random.default_rng(16)
+    T, M, eps = 7, 10, 0.05
+    x, y = _cloud(rng, T, 2), _cloud(rng, M, 2)
+    w = rng.uniform(0.5, 2.0, M)
+    a, b = np.full(T, 1.0 / T), w / w.sum()
+    Cxy = ((x[:, None] - y[None]) ** 2).sum(-1)
+    Cxx = ((x[:, None] - x[None]) ** 2).sum(-1)
+    Cyy = ((y[:, None] - y[None]) ** 2).sum(-1)
+    r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
+    assert r.resid > 1e-6                      # genuinely not converged
+    assert abs(np.max(np.abs(r.p_plus - r.p))) > 1e-6
+    assert abs(r.ot_ab - _dual(r.f_plus, r.g, a, b, Cxy, eps)) < 1e-13
+    assert abs(r.ot_aa - _dual(r.p_plus, r.p, a, a, Cxx, eps)) < 1e-13
+    assert abs(r.ot_bb - _dual(r.q_plus, r.q, b, b, Cyy, eps)) < 1e-13
+    c = _converge(x, y, w, eps=eps, tol=1e-13)
+    assert r.ot_ab <= c.ot_ab + 1e-13
+    assert r.ot_aa <= c.ot_aa + 1e-13
+    assert r.ot_bb <= c.ot_bb + 1e-13
+
+
 def _value_at(x, y, w, eps, init):
     r = oracle.sinkhorn(x, y, w, eps=eps, iters=50, init=init)
     while r.resid > 1e-14:

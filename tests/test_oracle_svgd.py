@@ -63,6 +63,21 @@ def test_median_bandwidth(n):
     assert oracle.median_bandwidth(x[:1]) == 1.0
 
 
+@pytest.mark.parametrize("shape", [(4, 4), (3, 3, 2)])
+def test_pair_count_on_lattice_ties_matches_brute_force(shape):
+    """Integer lattice points tie exactly at every squared distance they share,
+    so the strict and non-strict counts differ there; both against an explicit
+    double loop over the pairs i < j."""
+    x = np.array(list(np.ndindex(*shape)), dtype=np.float64)
+    n = len(x)
+    d2 = [float(((x[i] - x[j]) ** 2).sum()) for i in range(n) for j in range(i + 1, n)]
+    for thr in (0.5, 1.0, 1.5, 2.0, 4.0, 5.0, 100.0):
+        lt, le = oracle.pair_count(x, thr)
+        assert lt == sum(v < thr for v in d2), thr
+        assert le == sum(v <= thr for v in d2), thr
+    assert oracle.pair_count(x, 1.0)[1] > oracle.pair_count(x, 1.0)[0]
+
+
 def test_single_particle_phi_is_score():
     x = np.array([[0.3, 0.4]])
     s = np.array([[1.5, -2.0]])
