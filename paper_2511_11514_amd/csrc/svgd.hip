@@ -315,6 +315,43 @@ inline int bracket_grid(int T) {
     return std::min(ntr * ntc, kNumCU * 8);
 }
 
+// The pairs of one bracket tile: count those below the bracket, keep those in it
+// (the first kCandSlots per thread in LDS slots, the rest straight to the global
+// candidate list).  CHECK keeps only pairs with j > i (diagonal and ragged tiles).
+template <int D, int RB, bool CHECK>
+__device__ __forceinline__ void bracket_pairs(const float4* cj, int n, int j0, const float4 (&xi)[RB],
+                                              const int (&ir)[RB], unsigned lo, unsigned span,
+                                              unsigned& bl, unsigned& nin,
+                                              float (*slots)[256], MedState* st,
+                                              float* __restrict__ cand, unsigned long long cap) {
+    for (int jj = 0; jj < n; jj += 8) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const int jl = jj + g;
+            if (jl < n) {
+                const float4 xj = cj[jl];
+                const int j = j0 + jl;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const float d2 = sqdist<D>(xi[r], xj);
+                    const unsigned u = __float_as_uint(d2);
+                    const bool ok = !CHECK || j > ir[r];
+                    bl += (ok && u < lo) ? 1u : 0u;
+                    if (ok && u - lo <= span) {
+                        if (nin < (unsigned)kCandSlots) {
+                            slots[nin][threadIdx.x] = d2;
+                        } else {
+                            const unsigned long long gi = atomicAdd(&st->ncand, 1ull);
+                            if (gi < cap) cand[gi] = d2;
+                        }
+                        ++nin;
+                    }
+                }
+            }
+        }
+    }
+}
+
 template <int D>
 __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ c, int T,
                                                      const MedState* __restrict__ sst,
@@ -350,32 +387,12 @@ __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ 
         }
         unsigned nin = 0u, bl = 0u;
         const int n = j1 - j0;
-        for (int jj = 0; jj < n; jj += 8) {
-#pragma unroll
-            for (int g = 0; g < 8; ++g) {
-                const int jl = jj + g;
-                if (jl < n) {
-                    const float4 xj = cj[jl];
-                    const int j = j0 + jl;
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) {
-                        const float d2 = sqdist<D>(xi[r], xj);
-                        const unsigned u = __float_as_uint(d2);
-                        const bool ok = j > ir[r];
-                        bl += (ok && u < lo) ? 1u : 0u;
-                        if (ok && u - lo <= span) {
-                            if (nin < (unsigned)kCandSlots) {
-                                slots[nin][threadIdx.x] = d2;
-                            } else {
-                                const unsigned long long gi = atomicAdd(&st->ncand, 1ull);
-                                if (gi < cap) cand[gi] = d2;
-                            }
-                            ++nin;
-                        }
-                    }
-                }
-            }
-        }
+        // every row valid and below every column of the tile: no pair needs j > i
+        const bool off_diag = i0 + 256 * RB <= T && j0 >= i0 + 256 * RB;
+        if (off_diag)
+            bracket_pairs<D, RB, false>(cj, n, j0, xi, ir, lo, span, bl, nin, slots, st, cand, cap);
+        else
+            bracket_pairs<D, RB, true>(cj, n, j0, xi, ir, lo, span, bl, nin, slots, st, cand, cap);
         below += bl;
         // block exclusive prefix sum of the kept counts
         const unsigned kept = min(nin, (unsigned)kCandSlots);
