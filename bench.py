@@ -93,7 +93,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=40,
+    ap.add_argument("--cpu-iters", type=int, default=80,
                     help="Sinkhorn iterations of the CPU oracle sample")
     ap.add_argument("--no-svgd", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
