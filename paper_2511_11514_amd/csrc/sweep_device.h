@@ -470,6 +470,9 @@ __device__ __forceinline__ void merge_block(const Job& J, int q0, int nqpad, flo
 #pragma unroll
     for (int t = 0; t < D; ++t) b[t] = 0.f;
     if (q < J.nq) {
+        // unrolled so that the loads of several splits are in flight together; the
+        // partials are still combined in split order
+#pragma unroll 8
         for (int sp = wave; sp < J.splits; sp += 4) {
             const float* P = J.part + (size_t)sp * nqpad + q;
             float b2[D];
