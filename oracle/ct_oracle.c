@@ -7,8 +7,9 @@
  *
  * These are the O(N^2) sums of the method written out plainly in double
  * precision, one output point at a time, parallelised only across output
- * points (OpenMP).  No tiling, no fusion, no reordering of the sums beyond
- * "max first, then sum" for the log-sum-exp.  The iteration logic that calls
+ * points (OpenMP), and the log-sum-exp's loop over keys also across vector lanes
+ * (OpenMP simd).  No tiling, no fusion, no reordering of the sums beyond "max
+ * first, then sum" for the log-sum-exp and the lanes' partial sums.  The iteration logic that calls
  * them lives in oracle/sinkhorn.py and oracle/svgd.py.
  *
  *   orc_lse      : for query i,  z_ij = h_j - |xq_i - xk_j|^2 / eps,
@@ -22,6 +23,12 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
+
+/* glibc's vector exp (libmvec) for the simd loops of orc_lse; each lane is the
+ * correctly rounded exp to within a few ulp. */
+#pragma omp declare simd notinbranch
+double exp(double);
 
 static double sqdist(int d, const double* a, const double* b) {
     double s = 0.0;
@@ -32,31 +39,76 @@ static double sqdist(int d, const double* a, const double* b) {
     return s;
 }
 
+/* One query row of orc_lse, for a fixed d (inlined with d = 2 or 3 so that the
+ * loops over keys vectorise; the key coordinates come one array per axis).
+ * Pass 1 takes the largest exponent, pass 2 the shifted sum (and the weighted
+ * offsets).  The sums run over all keys; only the order in which the vector
+ * lanes add their terms differs from a one-at-a-time loop. */
+static inline __attribute__((always_inline)) void lse_row(
+    int d, const double* xi, int64_t nk, const double* k0, const double* k1, const double* k2,
+    const double* h, double eps, double* lse_i, double* bary_i) {
+    double m = -INFINITY;
+#pragma omp simd reduction(max : m)
+    for (int64_t j = 0; j < nk; ++j) {
+        double t0 = xi[0] - k0[j], t1 = xi[1] - k1[j];
+        double c = t0 * t0 + t1 * t1;
+        if (d == 3) {
+            double t2 = xi[2] - k2[j];
+            c += t2 * t2;
+        }
+        double z = h[j] - c / eps;
+        m = z > m ? z : m;
+    }
+    double s = 0.0, a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (!bary_i) {
+#pragma omp simd reduction(+ : s)
+        for (int64_t j = 0; j < nk; ++j) {
+            double t0 = xi[0] - k0[j], t1 = xi[1] - k1[j];
+            double c = t0 * t0 + t1 * t1;
+            if (d == 3) {
+                double t2 = xi[2] - k2[j];
+                c += t2 * t2;
+            }
+            s += exp(h[j] - c / eps - m);
+        }
+    } else {
+#pragma omp simd reduction(+ : s, a0, a1, a2)
+        for (int64_t j = 0; j < nk; ++j) {
+            double t0 = xi[0] - k0[j], t1 = xi[1] - k1[j];
+            double c = t0 * t0 + t1 * t1;
+            double t2 = 0.0;
+            if (d == 3) {
+                t2 = xi[2] - k2[j];
+                c += t2 * t2;
+            }
+            double e = exp(h[j] - c / eps - m);
+            s += e;
+            a0 -= e * t0;            /* e * (y_j - x_i) */
+            a1 -= e * t1;
+            if (d == 3) a2 -= e * t2;
+        }
+        bary_i[0] = a0 / s;
+        bary_i[1] = a1 / s;
+        if (d == 3) bary_i[2] = a2 / s;
+    }
+    *lse_i = m + log(s);
+}
+
 void orc_lse(int d, int64_t nq, const double* xq, int64_t nk, const double* xk,
              const double* h, double eps, double* lse, double* bary) {
+    /* key coordinates, one array per axis */
+    double* kc = (double*)malloc(sizeof(double) * (size_t)d * (size_t)nk);
+    for (int k = 0; k < d; ++k)
+        for (int64_t j = 0; j < nk; ++j) kc[k * nk + j] = xk[j * d + k];
+    const double* k2 = d == 3 ? kc + 2 * nk : kc;
 #pragma omp parallel for schedule(static) if (nq * nk > 65536)
     for (int64_t i = 0; i < nq; ++i) {
-        const double* xi = xq + i * d;
-        /* pass 1: the largest exponent */
-        double m = -INFINITY;
-        for (int64_t j = 0; j < nk; ++j) {
-            double z = h[j] - sqdist(d, xi, xk + j * d) / eps;
-            if (z > m) m = z;
-        }
-        /* pass 2: shifted sum (and weighted offsets) */
-        double s = 0.0;
-        double acc[3] = {0.0, 0.0, 0.0};
-        for (int64_t j = 0; j < nk; ++j) {
-            const double* xj = xk + j * d;
-            double e = exp(h[j] - sqdist(d, xi, xj) / eps - m);
-            s += e;
-            if (bary)
-                for (int k = 0; k < d; ++k) acc[k] += e * (xj[k] - xi[k]);
-        }
-        lse[i] = m + log(s);
-        if (bary)
-            for (int k = 0; k < d; ++k) bary[i * d + k] = acc[k] / s;
+        if (d == 2)
+            lse_row(2, xq + 2 * i, nk, kc, kc + nk, k2, h, eps, lse + i, bary ? bary + 2 * i : 0);
+        else
+            lse_row(3, xq + 3 * i, nk, kc, kc + nk, k2, h, eps, lse + i, bary ? bary + 3 * i : 0);
     }
+    free(kc);
 }
 
 void orc_svgd_phi(int d, int64_t n, const double* x, const double* score, double h, double* phi) {

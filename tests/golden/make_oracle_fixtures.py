@@ -6,6 +6,16 @@ named after its workload, holding the oracle's grad_x, grad_w, value, the
 gauge-comparable potentials and, for the Stein workloads, phi and h.
 
     python tests/golden/make_oracle_fixtures.py [name ...]
+
+The large 2-D workload at full size (T = 65536, M = 262144, eps = 0.002,
+K = 500; about 1.9e13 point pairs, hours on a few cores) is written without the
+reference self problem (its M x M iterations would add 3.4e13 pairs), so it
+holds the gradient and the cross and trajectory-self potentials but no value
+or weight gradient.  Its iterations run in chunks whose state is kept in
+CT_FIXTURE_CHECKPOINT (a directory, default the system's temporary one), so
+an interrupted run resumes where it stopped; the chunks continue the same
+iteration exactly (the oracle's warm start), so the result does not depend on
+the chunking.
 """
 import os
 import sys
@@ -25,6 +35,15 @@ SINKHORN = [
     ("grad_2d_full", "grad_2d", None, None, None),
     ("autograd_3d_T4096_M16384", "autograd_3d", 4096, 16384, None),
     ("roofline_2d_T4096_M16384", "roofline_2d", 4096, 16384, None),
+    ("autograd_3d_full", "autograd_3d", None, None, None),
+]
+# (fixture name, workload): full size, no reference self problem, chunked
+SINKHORN_NOREF = [
+    ("roofline_2d_full", "roofline_2d"),
+]
+# (fixture name, problems b of the ragged batch): their gradients only
+BATCH = [
+    ("batched_2d_sample16", list(range(0, 256, 16))),
 ]
 STEIN = [
     ("grad_2d_full_svgd", "grad_2d", None),
@@ -44,6 +63,54 @@ def sinkhorn_fixture(name, cfg_name, T, M, iters):
                         resid=r.resid)
     print(f"{name}: T={len(x)} M={len(y)} K={K} S={r.value:.6g} resid={r.resid:.2e} "
           f"({time.time() - t0:.0f} s)", flush=True)
+
+
+def sinkhorn_noref_fixture(name, cfg_name, chunk=25):
+    import tempfile
+    cfg = W.CONFIGS[cfg_name]
+    x, y, w, _g = W.config_inputs(cfg)
+    T, M, K = len(x), len(y), cfg.iters
+    ck_dir = os.environ.get("CT_FIXTURE_CHECKPOINT", tempfile.gettempdir())
+    ck = os.path.join(ck_dir, name + ".checkpoint.npz")
+    f, g, p, done = np.zeros(T), np.zeros(M), np.zeros(T), 0
+    if os.path.exists(ck):
+        c = np.load(ck, allow_pickle=False)
+        f, g, p, done = c["f"], c["g"], c["p"], int(c["done"])
+        print(f"{name}: resuming after {done} iterations", flush=True)
+    t0 = time.time()
+    zq = np.zeros(M)
+    while done < K:
+        n = min(chunk, K - done)
+        r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=n, want_value=False, want_grad_w=False,
+                            init=(f, g, p, zq))
+        f, g, p, done = r.f, r.g, r.p, done + n
+        np.savez(ck + ".tmp.npz", f=f, g=g, p=p, done=done)
+        os.replace(ck + ".tmp.npz", ck)
+        print(f"{name}: {done}/{K} iterations ({time.time() - t0:.0f} s)", flush=True)
+    r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=0, want_value=False, want_grad_w=False,
+                        init=(f, g, p, zq))
+    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload=cfg_name, T=T, M=M,
+                        eps=cfg.eps, iters=K, grad_x=r.grad_x, f=r.f, g=r.g, p=r.p,
+                        f_plus=r.f_plus, p_plus=r.p_plus)
+    print(f"{name}: T={T} M={M} K={K} ({time.time() - t0:.0f} s)", flush=True)
+
+
+def batch_fixture(name, problems):
+    cfg = W.CONFIGS["batched_2d"]
+    probs = W.batch_inputs(cfg)
+    t0 = time.time()
+    Ts, Ms, grads = [], [], []
+    for b in problems:
+        x, y, w = probs[b]
+        r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=cfg.iters, want_value=False,
+                            want_grad_w=False)
+        Ts.append(len(x))
+        Ms.append(len(y))
+        grads.append(r.grad_x)
+    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload="batched_2d",
+                        problems=np.array(problems), T=np.array(Ts), M=np.array(Ms),
+                        eps=cfg.eps, iters=cfg.iters, grad_x=np.concatenate(grads))
+    print(f"{name}: {len(problems)} problems ({time.time() - t0:.0f} s)", flush=True)
 
 
 def stein_fixture(name, cfg_name, T):
@@ -66,3 +133,9 @@ if __name__ == "__main__":
     for spec in SINKHORN:
         if not want or spec[0] in want:
             sinkhorn_fixture(*spec)
+    for spec in BATCH:
+        if not want or spec[0] in want:
+            batch_fixture(*spec)
+    for spec in SINKHORN_NOREF:
+        if not want or spec[0] in want:
+            sinkhorn_noref_fixture(*spec)
