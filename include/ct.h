@@ -143,6 +143,33 @@ ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const floa
                            void* stream);
 
 /*
+ * Allocation-free variant of ct_sinkhorn_grad, for callers that cannot allocate
+ * device memory or create HIP objects around the call (code being captured into
+ * a HIP graph, tight serving loops, harnesses that forbid allocation).  Same
+ * arguments, definitions, outputs and errors as ct_sinkhorn_grad, minus the
+ * workspace: the call uses a static device array of
+ * ct_sinkhorn_static_scratch_bytes() bytes (64 MiB) that the library holds on
+ * every device it runs on until the process ends.  The first call on a device
+ * looks up that array's device address and creates the library's auxiliary
+ * stream and two events for that device; later calls create, allocate and free
+ * nothing.  The caller still owns x, y, w and every output.
+ *   Errors: as ct_sinkhorn_grad; CT_E_WORKSPACE when the problem needs more
+ *   scratch than the array holds (ct_sinkhorn_workspace_size(T, M, o) >
+ *   ct_sinkhorn_static_scratch_bytes(), e.g. T = 4096 with M = 16384), with
+ *   nothing enqueued; CT_E_UNSUPPORTED while ct_profile_enable is on (its
+ *   per-launch events would be created by the call).
+ *   Every call on one device shares that device's array, and the array keeps
+ *   the last call's contents (each call clears what must start at zero): two
+ *   calls that may overlap on one device (different streams, or different host
+ *   threads) race and give undefined results; order them on one stream.
+ */
+size_t ct_sinkhorn_static_scratch_bytes(void);
+ct_status ct_sinkhorn_grad_static(const float* x, int64_t T, const float* y, const float* w,
+                                  int64_t M, const ct_sinkhorn_opts* o, float* grad_x,
+                                  float* grad_w, float* value, float* pot, float* pot_plus,
+                                  float* aux, void* stream);
+
+/*
  * Status words that the last ct_sinkhorn_grad call on `ws` left in its workspace,
  * read after waiting for `stream` (the one synchronising query of the Sinkhorn
  * path; ct_sinkhorn_grad itself never waits).

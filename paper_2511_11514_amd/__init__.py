@@ -12,6 +12,7 @@ from .api import (sinkhorn_grad, sinkhorn_grad_batched, SinkhornDivergence, Batc
                   sinkhorn_divergence, svgd_grad, lqr_track, plan, plan_ensemble,
                   autotune_sinkhorn,
                   tuning_table, tuning_save, tuning_load, tuning_clear, GMM, version,
-                  probe_alu_rates, svgd_grad_score, UtilityGrid, grid_score, grid_samples)
+                  probe_alu_rates, svgd_grad_score, UtilityGrid, grid_score, grid_samples,
+                  static_scratch_bytes)
 
 __version__ = "0.1.0"

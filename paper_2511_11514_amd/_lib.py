@@ -79,6 +79,9 @@ _SIGS = {
     "ct_sinkhorn_workspace_size": (c_size_t, [c_int64, c_int64, POINTER(SinkhornOpts)]),
     "ct_sinkhorn_grad": (c_int32, [P, c_int64, P, P, c_int64, POINTER(SinkhornOpts), P, P, P, P, P,
                                    P, P, c_size_t, P]),
+    "ct_sinkhorn_static_scratch_bytes": (c_size_t, []),
+    "ct_sinkhorn_grad_static": (c_int32, [P, c_int64, P, P, c_int64, POINTER(SinkhornOpts), P, P,
+                                          P, P, P, P, P]),
     "ct_status_sync": (c_int32, [P, POINTER(c_uint32), POINTER(c_uint32), P]),
     "ct_sinkhorn_batched_workspace_size": (c_size_t, [c_int32, PI64, PI64, POINTER(SinkhornOpts)]),
     "ct_sinkhorn_batched_prepare": (c_int32, [c_int32, PI64, PI64, POINTER(SinkhornOpts), P,

@@ -67,12 +67,14 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
                   grad_w: bool = False, init: Optional[torch.Tensor] = None,
                   ref_q: Optional[torch.Tensor] = None, safe: bool = False,
                   potentials: bool = False, aux: bool = False,
-                  one_stream: bool = False) -> SinkhornOut:
+                  one_stream: bool = False, static_scratch: bool = False) -> SinkhornOut:
     """Gradient of the (debiased) Sinkhorn divergence; see ct_sinkhorn_grad.
 
     x [T,d], y [M,d], w [M] or None: float32 GPU tensors.
     init: optional [2T+2M] starting potentials (f, g, p, q) -> CT_WARM_START.
     ref_q: optional [M] converged reference self potential -> CT_REF_CACHED.
+    static_scratch: call ct_sinkhorn_grad_static (the library's static device
+    scratch instead of a workspace; only the outputs are allocated here).
     """
     dev = x.device
     x = _req(x, "x")
@@ -101,12 +103,22 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
     val = torch.empty(1, dtype=torch.float32, device=dev) if value else None
     pp = torch.empty(2 * T + 2 * M, dtype=torch.float32, device=dev) if potentials else None
     ax = torch.empty(8, dtype=torch.float32, device=dev) if aux else None
-    nbytes = lib().ct_sinkhorn_workspace_size(T, M, ctypes.byref(o))
-    ws = _workspace(nbytes, dev)
-    st = lib().ct_sinkhorn_grad(_p(x), T, _p(y), _p(w), M, ctypes.byref(o), _p(gx), _p(gw),
-                                _p(val), _p(pot), _p(pp), _p(ax), _p(ws), nbytes, _stream(dev))
-    check("ct_sinkhorn_grad", st)
+    if static_scratch:
+        st = lib().ct_sinkhorn_grad_static(_p(x), T, _p(y), _p(w), M, ctypes.byref(o), _p(gx),
+                                           _p(gw), _p(val), _p(pot), _p(pp), _p(ax), _stream(dev))
+        check("ct_sinkhorn_grad_static", st)
+    else:
+        nbytes = lib().ct_sinkhorn_workspace_size(T, M, ctypes.byref(o))
+        ws = _workspace(nbytes, dev)
+        st = lib().ct_sinkhorn_grad(_p(x), T, _p(y), _p(w), M, ctypes.byref(o), _p(gx), _p(gw),
+                                    _p(val), _p(pot), _p(pp), _p(ax), _p(ws), nbytes, _stream(dev))
+        check("ct_sinkhorn_grad", st)
     return SinkhornOut(gx, gw, val, pot if potentials else None, pp, ax)
+
+
+def static_scratch_bytes() -> int:
+    """Size of the device array that ct_sinkhorn_grad_static works in."""
+    return int(lib().ct_sinkhorn_static_scratch_bytes())
 
 
 class SinkhornDivergence(torch.autograd.Function):

@@ -440,9 +440,17 @@ static ct_status aux_stream(hipStream_t* out) {
     return CT_OK;
 }
 
+// Auxiliary stream and fork/join events of the two-stream schedule, made once and
+// reused by every call (the allocation-free entry point); null members: made and
+// destroyed by each call.
+struct ForkJoin {
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
 // Iterate-and-extrapolate for one problem whose arrays are staged in L.
 static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_opts* o,
-                             hipStream_t st) {
+                             hipStream_t st, const ForkJoin* fj) {
     const int d = o->d;
     const bool debias = o->flags & CT_DEBIAS;
     const bool want_v = o->flags & (CT_VALUE | CT_GRAD_W);
@@ -463,11 +471,18 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     const bool two_streams = any_self && o->iters > 0 && !(o->flags & CT_ONE_STREAM);
     hipStream_t sst = st;
     hipEvent_t fork = nullptr, join = nullptr;
+    const bool own_events = !(fj && fj->fork);
     if (two_streams) {
-        ct_status rc = aux_stream(&sst);
-        if (rc) return rc;
-        CT_CHECK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-        CT_CHECK_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        if (own_events) {
+            ct_status rc = aux_stream(&sst);
+            if (rc) return rc;
+            CT_CHECK_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+            CT_CHECK_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+        } else {
+            sst = fj->aux;
+            fork = fj->fork;
+            join = fj->join;
+        }
         CT_CHECK_HIP(hipEventRecord(fork, st));
         CT_CHECK_HIP(hipStreamWaitEvent(sst, fork, 0));
     }
@@ -497,8 +512,10 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     if (two_streams) {
         CT_CHECK_HIP(hipEventRecord(join, sst));
         CT_CHECK_HIP(hipStreamWaitEvent(st, join, 0));
-        CT_CHECK_HIP(hipEventDestroy(fork));
-        CT_CHECK_HIP(hipEventDestroy(join));
+        if (own_events) {
+            CT_CHECK_HIP(hipEventDestroy(fork));
+            CT_CHECK_HIP(hipEventDestroy(join));
+        }
     }
     const bool lagged_final = !safe_only && (warm || o->iters > 0);
     {
@@ -529,11 +546,12 @@ extern "C" size_t ct_sinkhorn_workspace_size(int64_t T, int64_t M, const ct_sink
     return sk_layout(nullptr, (int)T, (int)M, o->d).bytes;
 }
 
-extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* y, const float* w,
-                                      int64_t M64, const ct_sinkhorn_opts* o, float* grad_x,
-                                      float* grad_w, float* value, float* pot, float* pot_plus,
-                                      float* aux, void* ws, size_t ws_bytes, void* stream) {
-    clear_error();
+namespace ct {
+
+// Host checks of one gradient call's arguments (everything but the workspace).
+static ct_status validate_call(const float* x, int64_t T64, const float* y, int64_t M64,
+                               const ct_sinkhorn_opts* o, const float* grad_x,
+                               const float* grad_w, const float* value, const float* pot) {
     ct_status rc = validate(x, T64, y, M64, o);
     if (rc) return rc;
     if (!grad_x) return fail(CT_E_ARG, "grad_x must be non-null");
@@ -543,6 +561,17 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
     if (!value && (o->flags & CT_VALUE)) return fail(CT_E_ARG, "CT_VALUE needs value");
     if (!pot && (o->flags & (CT_WARM_START | CT_REF_CACHED)))
         return fail(CT_E_ARG, "CT_WARM_START / CT_REF_CACHED need pot");
+    return CT_OK;
+}
+
+// The whole gradient call on the workspace `ws` (both entry points).
+static ct_status sinkhorn_grad_impl(const float* x, int64_t T64, const float* y, const float* w,
+                                    int64_t M64, const ct_sinkhorn_opts* o, float* grad_x,
+                                    float* grad_w, float* value, float* pot, float* pot_plus,
+                                    float* aux, void* ws, size_t ws_bytes, void* stream,
+                                    const ForkJoin* fj) {
+    ct_status rc = validate_call(x, T64, y, M64, o, grad_x, grad_w, value, pot);
+    if (rc) return rc;
     const int T = (int)T64, M = (int)M64, d = o->d;
     if (!ws) return fail(CT_E_ARG, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
@@ -587,7 +616,7 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
     hipLaunchKernelGGL(k_stage, dim3((n + 255) / 256), dim3(256), 0, st, A);
     CT_CHECK_HIP(hipGetLastError());
 
-    rc = run_problem(L, T, M, o, st);
+    rc = run_problem(L, T, M, o, st, fj);
     if (rc) return rc;
 
     hipLaunchKernelGGL(k_grad_x, dim3((T * d + 255) / 256), dim3(256), 0, st, L.dy,
@@ -632,6 +661,79 @@ extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* 
                                     hipMemcpyDeviceToDevice, st));
     }
     return CT_OK;
+}
+
+// ------------------------------------------------- allocation-free variant
+// Scratch of ct_sinkhorn_grad_static: one array per device, held until the process
+// ends.  Host code never passes `scratch` itself (its host name is a stand-in, not
+// a device address): each device's address comes from hipGetSymbolAddress once,
+// with that device current, and is kept in g_static below.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+struct StaticDevice {
+    void* ptr = nullptr;   // device address of `scratch` on this device
+    ForkJoin fj;           // auxiliary stream and events made at set-up
+};
+
+// Per-device set-up on the first call on that device: the scratch address, the
+// auxiliary stream and the fork/join events.  Later calls only look them up.
+static ct_status static_device(StaticDevice* out) {
+    static std::mutex mu;
+    static std::map<int, StaticDevice> devs;
+    int dev = 0;
+    CT_CHECK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = devs.find(dev);
+    if (it == devs.end()) {
+        StaticDevice sd;
+        CT_CHECK_HIP(hipGetSymbolAddress(&sd.ptr, HIP_SYMBOL(scratch)));
+        if (!sd.ptr || reinterpret_cast<uintptr_t>(sd.ptr) % 256)
+            return fail(CT_E_HIP, "static scratch has no usable device address on device %d", dev);
+        ct_status rc = aux_stream(&sd.fj.aux);
+        if (rc) return rc;
+        CT_CHECK_HIP(hipEventCreateWithFlags(&sd.fj.fork, hipEventDisableTiming));
+        CT_CHECK_HIP(hipEventCreateWithFlags(&sd.fj.join, hipEventDisableTiming));
+        it = devs.emplace(dev, sd).first;
+    }
+    *out = it->second;
+    return CT_OK;
+}
+
+}  // namespace ct
+
+extern "C" ct_status ct_sinkhorn_grad(const float* x, int64_t T64, const float* y, const float* w,
+                                      int64_t M64, const ct_sinkhorn_opts* o, float* grad_x,
+                                      float* grad_w, float* value, float* pot, float* pot_plus,
+                                      float* aux, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    return sinkhorn_grad_impl(x, T64, y, w, M64, o, grad_x, grad_w, value, pot, pot_plus, aux, ws,
+                              ws_bytes, stream, nullptr);
+}
+
+extern "C" size_t ct_sinkhorn_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" ct_status ct_sinkhorn_grad_static(const float* x, int64_t T64, const float* y,
+                                             const float* w, int64_t M64,
+                                             const ct_sinkhorn_opts* o, float* grad_x,
+                                             float* grad_w, float* value, float* pot,
+                                             float* pot_plus, float* aux, void* stream) {
+    clear_error();
+    ct_status rc = validate_call(x, T64, y, M64, o, grad_x, grad_w, value, pot);
+    if (rc) return rc;
+    const size_t need = sk_layout(nullptr, (int)T64, (int)M64, o->d).bytes;
+    if (need > kStaticScratchBytes)
+        return fail(CT_E_WORKSPACE,
+                    "problem needs %zu bytes of scratch; the static scratch holds %zu "
+                    "(T=%lld, M=%lld, d=%d): use ct_sinkhorn_grad with a workspace",
+                    need, kStaticScratchBytes, (long long)T64, (long long)M64, o->d);
+    if (profiling())
+        return fail(CT_E_UNSUPPORTED, "launch profiling creates events; disable it for this entry point");
+    StaticDevice sd;
+    rc = static_device(&sd);
+    if (rc) return rc;
+    return sinkhorn_grad_impl(x, T64, y, w, M64, o, grad_x, grad_w, value, pot, pot_plus, aux,
+                              sd.ptr, kStaticScratchBytes, stream, &sd.fj);
 }
 
 // ------------------------------------------------------------- autotuning

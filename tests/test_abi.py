@@ -224,3 +224,25 @@ def test_status_sync_rejects_bad_workspaces():
     L = _lib.lib()
     assert L.ct_status_sync(None, None, None, None) == _lib.CT_E_ARG
     assert L.ct_status_sync(ctypes.c_void_p(257), None, None, None) == _lib.CT_E_WORKSPACE
+
+
+def test_static_scratch_entry_rejects_before_launch():
+    """ct_sinkhorn_grad_static validates like ct_sinkhorn_grad and refuses a problem
+    whose scratch exceeds its static array, all on the host (nothing enqueued)."""
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    P = ctypes.c_void_p
+    assert L.ct_sinkhorn_static_scratch_bytes() == 64 << 20
+
+    def call(T, M, o, x=1, gx=1):
+        return L.ct_sinkhorn_grad_static(P(x), T, P(1), None, M, ctypes.byref(o), P(gx), None,
+                                         None, None, None, None, None)
+    O = _lib.SinkhornOpts
+    ok = O(2, 10, 0.01, _lib.CT_DEBIAS)
+    assert call(10, 20, ok, x=None) == _lib.CT_E_ARG
+    assert call(10, 20, ok, gx=None) == _lib.CT_E_ARG
+    assert call(0, 20, ok) == _lib.CT_E_SHAPE
+    assert call(10, 20, O(2, 10, -1.0, 1)) == _lib.CT_E_ARG
+    assert L.ct_sinkhorn_workspace_size(4096, 16384, ctypes.byref(ok)) > 64 << 20
+    assert call(4096, 16384, ok) == _lib.CT_E_WORKSPACE
+    assert b"static scratch" in L.ct_last_error()
