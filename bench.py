@@ -1,12 +1,17 @@
 """Benchmark of the coverage-flow hot path on one MI355X.
 
-One step = one full gradient pass of the 2D gradient-field workload
-(T=4096 trajectory samples on a smooth random walk, M=16384 reference samples
-from a 5-component Gaussian mixture): the debiased Sinkhorn divergence
-(eps=0.005, 200 iterations) through its autograd form (value, gradient with
-respect to the samples and to the reference weights, i.e. cross, self and
-reference-self solves plus the extrapolation pass), and the Stein flow on the
-same samples (mixture score, median bandwidth, T x T sum).
+One step = one full gradient pass of the large 2-D workload (T = 65536 samples of
+a unicycle trajectory, M = 262144 reference samples from a 16-component Gaussian
+mixture with a 10 % uniform floor): the debiased Sinkhorn divergence (eps = 0.002,
+500 iterations) through its autograd form (value, gradient with respect to the
+samples and to the reference weights: cross and trajectory-self solves plus the
+extrapolation pass, with the reference self potential computed once per
+reference outside the timed steps because it does not depend on the trajectory),
+and the Stein flow on the same samples (mixture score, median bandwidth, T x T
+sum).  Legs beside it: the 2-D gradient-field workload (T = 4096, M = 16384), the
+3-D autograd workload (T = 16384, M = 65536), the Stein flow alone, the
+256-problem ragged batch (eager and graph-replayed against plain calls) and the
+FP64 oracle on the host cores.
 
 Prints one JSON line.  `value` is the pair evaluations (one exp each) of the
 step divided by the step's wall time on the GPU stream.
@@ -63,28 +68,109 @@ def sweep_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def pairs_per_pass(T: int, M: int, K: int, debias=True, ref=True, value=True) -> float:
-    per_iter = 2.0 * T * M + (T * T if debias else 0) + (M * M if ref else 0)
+def pairs_per_pass(T: int, M: int, K: int, debias=True, ref=True, value=True,
+                   ref_cached=False) -> float:
+    """Point pairs (one exp each) of one gradient pass: K iterations of the cross,
+    trajectory-self and (unless cached) reference-self sweeps, then the final pass."""
+    per_iter = 2.0 * T * M + (T * T if debias else 0) + (M * M if ref and not ref_cached else 0)
     final = T * M + (T * T if debias else 0) + ((T * M + (M * M if ref else 0)) if value else 0)
     return K * per_iter + final
 
 
-def cpu_baseline(x, y, w, g, eps, iters_sample: int) -> dict:
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+def omp_threads() -> int:
+    """Threads the oracle's OpenMP loops use: OMP_NUM_THREADS, else every CPU this
+    process may run on."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    return int(v) if v.strip().isdigit() else len(os.sched_getaffinity(0))
+
+
+_ONE_CORE = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import oracle
+import workloads as W
+cfg = W.CONFIGS["roofline_2d"]
+x, y, w, _g = W.config_inputs(cfg)
+x = x[:{rows}]
+logb = np.log(w.astype(np.float64) / np.sum(w, dtype=np.float64))
+oracle.lse_update(x[:16], y, logb, np.zeros(len(y)), cfg.eps)
+t0 = time.perf_counter()
+oracle.lse_update(x, y, logb, np.zeros(len(y)), cfg.eps)
+print(json.dumps({{"pairs": float(len(x)) * len(y), "s": time.perf_counter() - t0}}))
+"""
+
+
+def cpu_baseline(x, y, w, eps, iters_sample: int, one_core_rows: int = 2048) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the headline workload:
+    `iters_sample` Sinkhorn iterations (cross and trajectory-self solves) and the
+    final pass over the full inputs on every host thread, and one soft-min update
+    of `one_core_rows` trajectory rows against all reference samples on one core
+    (a child process with OMP_NUM_THREADS=1)."""
+    import subprocess
     import numpy as np
     import oracle
     T, M = len(x), len(y)
+    z = np.zeros(16)
+    oracle.lse_update(x[:16], y[:16], z, z, eps)   # load the C library
     t0 = time.perf_counter()
-    oracle.sinkhorn(x, y, w, eps=eps, iters=iters_sample, want_value=True, want_grad_w=True)
-    sc = oracle.gmm_score(x, g.weights, g.means, g.sigmas, g.floor)
-    h = oracle.median_bandwidth(x)
-    oracle.svgd_phi(x, sc, h)
+    oracle.sinkhorn(x, y, w, eps=eps, iters=iters_sample, want_value=False, want_grad_w=False)
     dt = time.perf_counter() - t0
-    pairs = pairs_per_pass(T, M, iters_sample) + T * T
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs / dt, "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"same inputs, {iters_sample} Sinkhorn iterations + extrapolation pass "
-                      f"(value, grad_x, grad_w) + Stein flow: {pairs:.3e} pairs in {dt:.1f} s"}
+    pairs = pairs_per_pass(T, M, iters_sample, ref=False, value=False)
+    res = {"value": pairs / dt, "unit": "pair-evals/s", "cores": omp_threads(), "kind": "oracle",
+           "sample": f"same inputs (T={T}, M={M}), {iters_sample} Sinkhorn iterations of the "
+                     f"cross and trajectory-self solves + the final pass (grad_x): "
+                     f"{pairs:.3e} pairs in {dt:.1f} s"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_CORE.format(root=ROOT, rows=one_core_rows)],
+                       env=env, stdout=subprocess.PIPE, text=True, check=True)
+    one = json.loads(r.stdout.strip().splitlines()[-1])
+    res["one_core"] = {"value": one["pairs"] / one["s"], "unit": "pair-evals/s", "cores": 1,
+                       "sample": f"one soft-min update of {one_core_rows} trajectory rows "
+                                 f"against all {M} reference samples: {one['pairs']:.3e} pairs "
+                                 f"in {one['s']:.2f} s"}
+    return res
+
+
+def read_profile(L, _lib) -> list:
+    """Launch records of ct_profile_*: (kind0, kind1, pairs, ms) per launch."""
+    kind = (ctypes.c_int32 * 4)()
+    pr, t = ctypes.c_double(), ctypes.c_float()
+    out = []
+    for i in range(L.ct_profile_count()):
+        _lib.check("ct_profile_read", L.ct_profile_read(i, kind, ctypes.byref(pr), ctypes.byref(t)))
+        out.append((kind[0], kind[1], pr.value, t.value))
+    L.ct_profile_clear()
+    return out
+
+
+def dominant_sweeps(recs) -> tuple:
+    """(pairs, ms, launches) of the lagged-shift sweeps without offsets."""
+    sel = [r for r in recs if r[0] == 1 and r[1] == 0]
+    return sum(r[2] for r in sel), sum(r[3] for r in sel), len(sel)
+
+
+def sinkhorn_step(ct, x, y, w, eps, K, gmm=None, ref_q=None, one_stream=False):
+    """One gradient pass: S, dS/dx and dS/dw through the autograd form, then the
+    Stein flow on the same samples when a mixture is given."""
+    def step():
+        xr = x.detach().requires_grad_(True)
+        wr = w.detach().requires_grad_(True)
+        S = ct.sinkhorn_divergence(xr, y, wr, eps=eps, iters=K, one_stream=one_stream,
+                                   ref_q=ref_q)
+        S.backward()
+        out = [S, xr.grad, wr.grad]
+        if gmm is not None:
+            out.append(ct.svgd_grad(x, gmm)[0])
+        return out
+    return step
+
+
+def rel_err(a, b) -> float:
+    import numpy as np
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 def main() -> int:
@@ -93,14 +179,21 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-iters", type=int, default=80,
-                    help="Sinkhorn iterations of the CPU oracle sample")
-    ap.add_argument("--no-svgd", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2,
+                    help="Sinkhorn iterations of the CPU oracle sample (large workload)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="only the headline step (no 2-D, 3-D, Stein and batched legs)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
+    ap.add_argument("--two-stream", action="store_true",
+                    help="run the self sweeps of the headline step on the library's auxiliary "
+                         "stream (default: one stream, as every launch fills the GPU)")
+    ap.add_argument("--events-separately", action="store_true",
+                    help="take the per-launch events in one extra step instead of in the timed "
+                         "steps")
     ap.add_argument("--autotune", action="store_true",
                     help="re-tune the sweep schedules instead of loading the stored tuning table")
     ap.add_argument("--graph", action="store_true",
-                    help="also time the step captured into a HIP graph (replays)")
+                    help="also time the 2-D leg's step captured into a HIP graph (replays)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB buffer (reference kernel for HBM counters)")
     ap.add_argument("--horizon-sweep", action="store_true",
@@ -112,6 +205,9 @@ def main() -> int:
     ap.add_argument("--grid", action="store_true",
                     help="instead of the benchmark line: flows toward a continuous utility map "
                          "on a grid (Stein flow on its score, Sinkhorn flow on its weighted nodes)")
+    ap.add_argument("--grad-2d-only", action="store_true",
+                    help="instead of the benchmark line: only the 2-D gradient-field leg "
+                         "(T = 4096, M = 16384), for profiling its launches")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -142,111 +238,78 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cfg = W.CONFIGS["grad_2d"]
+    L = _lib.lib()
+    # sweep schedules: the stored table written by the autotuner on an MI355X
+    table = os.path.join(ROOT, "paper_2511_11514_amd", "tuning", "mi355x.txt")
+    tuned = "stored table " + os.path.relpath(table, ROOT)
+    if args.autotune or not os.path.exists(table):
+        tuned = None
+    else:
+        ct.tuning_load(table)
+    if args.grad_2d_only:
+        print(json.dumps(grad_2d_leg(ct, torch, dev, L, _lib, tuned, steps=args.steps,
+                                     warmup=args.warmup, graph=args.graph)))
+        return 0
+
+    # headline: one gradient pass of the large 2-D workload (unicycle trajectory
+    # samples T = 65536, M = 262144 reference samples of a 16-component mixture with
+    # a 10 % uniform floor, eps = 0.002, K = 500): S, dS/dx, dS/dw through autograd
+    # with the reference self potential computed once per reference (it does not
+    # depend on the trajectory), plus the Stein flow on the same samples
+    cfg = W.CONFIGS["roofline_2d"]
     T, M, d, eps, K = cfg.T, cfg.M, cfg.d, cfg.eps, cfg.iters
     x_np, y_np, w_np, g_np = W.config_inputs(cfg)
     x = torch.as_tensor(x_np, device=dev)
     y = torch.as_tensor(y_np, device=dev)
     w = torch.as_tensor(w_np, device=dev)
     gmm = ct.GMM.from_numpy(g_np, dev)
-    use_svgd = not args.no_svgd
-
-    def step(one_stream=False):
-        xr = x.detach().requires_grad_(True)
-        wr = w.detach().requires_grad_(True)
-        S = ct.sinkhorn_divergence(xr, y, wr, eps=eps, iters=K, one_stream=one_stream)
-        S.backward()
-        out = [S, xr.grad, wr.grad]
-        if use_svgd:
-            out.append(ct.svgd_grad(x, gmm)[0])
-        return out
-
-    # sweep schedules for this shape: the stored table written by the autotuner on
-    # an MI355X, or a fresh tuning run (outside the timed region)
-    table = os.path.join(ROOT, "paper_2511_11514_amd", "tuning", "mi355x.txt")
-    if args.autotune or not os.path.exists(table):
+    if tuned is None:
         ct.autotune_sinkhorn(T, M, d, eps)
         tuned = "autotuned in this run"
-    else:
-        ct.tuning_load(table)
-        tuned = "stored table " + os.path.relpath(table, ROOT)
-    try:
-        step()
-    except ct.CtError as e:
-        if e.code != _lib.CT_E_UNSUPPORTED:
-            raise
-        use_svgd = False
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ref_q = ct.reference_self_potential(y, w, eps=eps, iters=K)
+    e1.record()
+    torch.cuda.synchronize()
+    ref_ms = e0.elapsed_time(e1)
+    print(f"# reference self potential: {ref_ms:.0f} ms", file=sys.stderr, flush=True)
+    step = sinkhorn_step(ct, x, y, w, eps, K, gmm=gmm, ref_q=ref_q,
+                         one_stream=not args.two_stream)
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"# warm-up step {i + 1}/{args.warmup}", file=sys.stderr, flush=True)
+    live_events = not args.events_separately
+    L.ct_profile_clear()
+    if live_events:
+        L.ct_profile_enable(1)
+    torch.cuda.synchronize()
     e0.record()
     for _ in range(args.steps):
         out = step()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    assert all(torch.isfinite(t).all().item() for t in out)
-
-    graph_ms = None
-    if args.graph:
-        side = torch.cuda.Stream()
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            step()
-        torch.cuda.current_stream().wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            gout = step()
-        graph.replay()
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.steps):
-            graph.replay()
-        e1.record()
-        torch.cuda.synchronize()
-        graph_ms = e0.elapsed_time(e1) / args.steps
-        assert all(torch.isfinite(t).all().item() for t in gout)
-        assert torch.allclose(gout[1], out[1], rtol=0, atol=0)
-
-    sk_pairs = pairs_per_pass(T, M, K)
-    svgd_pairs = T * T if use_svgd else 0
-    total_pairs = sk_pairs + svgd_pairs
-
-    # live per-launch timing of the dominant kernel (the lagged-shift sweep): one
-    # more step with the same launches serialised on one stream: each sweep kernel
-    # runs alone and carries a pair of events stamped with its own start and end
-    # (recording them inside the two-stream timed steps slows the host enqueue by
-    # about a third, so they are taken in this extra step)
-    L = _lib.lib()
-    L.ct_profile_clear()
-    L.ct_profile_enable(1)
-    step(one_stream=True)
-    torch.cuda.synchronize()
     L.ct_profile_enable(0)
-    kind = (ctypes.c_int32 * 4)()
-    pr = ctypes.c_double()
-    t = ctypes.c_float()
-    dom_pairs = dom_ms = 0.0
-    n_dom = 0
-    all_ms = 0.0
-    for i in range(L.ct_profile_count()):
-        _lib.check("ct_profile_read", L.ct_profile_read(i, kind, ctypes.byref(pr), ctypes.byref(t)))
-        all_ms += t.value
-        if kind[0] == 1 and kind[1] == 0:
-            dom_pairs += pr.value
-            dom_ms += t.value
-            n_dom += 1
-    L.ct_profile_clear()
+    ms = e0.elapsed_time(e1) / args.steps
+    print(f"# timed {args.steps} steps: {ms:.1f} ms each", file=sys.stderr, flush=True)
+    assert all(torch.isfinite(t).all().item() for t in out)
+    if not live_events:
+        L.ct_profile_enable(1)
+        step()
+        torch.cuda.synchronize()
+        L.ct_profile_enable(0)
+    recs = read_profile(L, _lib)
+    dom_pairs, dom_ms, n_dom = dominant_sweeps(recs)
+    sk_pairs = pairs_per_pass(T, M, K, ref_cached=True)
+    svgd_pairs = T * T
+    total_pairs = sk_pairs + svgd_pairs
     ach = dom_pairs / (dom_ms * 1e-3) / 1e12
     peak = pair_roof(d, NOMINAL_RATES) / 1e12
     probe = ct.probe_alu_rates(str(dev))
     probe_peak = pair_roof(d, probe, clock=probe["clock_hz"]) / 1e12
     traffic = None
-    tf = os.path.join(ROOT, "profiles", "sweep_traffic_grad_2d.json")
+    tf = os.path.join(ROOT, "profiles", "sweep_traffic_roofline_2d.json")
     if os.path.exists(tf):
         with open(tf) as fh:
             rec = json.load(fh)
@@ -267,15 +330,19 @@ def main() -> int:
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"grad_2d: d=2 T={T} M={M} (5-component GMM reference, random-walk "
-                        f"trajectory), Sinkhorn eps={eps} K={K} debiased with value+grad_x+grad_w "
-                        f"via autograd" + (", plus Stein flow (median bandwidth)" if use_svgd else ""),
+            "workload": f"roofline_2d: d=2 T={T} unicycle-trajectory samples, M={M} reference "
+                        f"samples (16-component GMM + 10% uniform floor), Sinkhorn eps={eps} "
+                        f"K={K} debiased, S + dS/dx + dS/dw via autograd with the reference "
+                        f"self potential cached per reference, plus Stein flow (median "
+                        f"bandwidth)",
             "pairs_per_step": total_pairs,
             "sinkhorn_pairs": sk_pairs,
             "svgd_pairs": svgd_pairs,
             "tm_pair_evals_per_s": K * T * M / (ms * 1e-3),
+            "streams": 2 if args.two_stream else 1,
             "schedules": tuned,
-            "graph_ms_per_step": graph_ms,
+            "reference_self_potential_ms": ref_ms,
+            "reference_self_pairs": float(K) * M * M,
         },
         "roofline": {
             "bound": "alu",
@@ -287,6 +354,7 @@ def main() -> int:
             "traffic": traffic,
             "launches": n_dom,
             "avg_launch_us": dom_ms / max(n_dom, 1) * 1e3,
+            "events": "in the timed steps" if live_events else "one extra step",
             "pair_mix": pair_mix(d),
             "nominal_lanes_per_clk_per_cu": NOMINAL_RATES,
             "probe": {k: round(v, 4) for k, v in probe.items()},
@@ -294,17 +362,109 @@ def main() -> int:
             "frac_of_probe_peak": ach / probe_peak,
         },
     }
-    res["parity"] = parity_vs_stored_oracle(out, ct, torch, dev)
+    res["parity"] = parity_roofline_2d(out, x_np)
     res["system"] = system_info(torch, dev)
-    res["autograd_3d"] = autograd_3d_leg(ct, torch, dev)
-    if use_svgd:
+    del out, step, ref_q
+    if not args.no_legs:
+        res["grad_2d"] = grad_2d_leg(ct, torch, dev, L, _lib, tuned, graph=args.graph)
+        print("# 2-D leg done", file=sys.stderr, flush=True)
+        res["autograd_3d"] = autograd_3d_leg(ct, torch, dev)
+        print("# 3-D leg done", file=sys.stderr, flush=True)
         res["stein"] = stein_leg(ct, torch, dev, L, _lib)
-    if not args.no_batched:
-        res["batched"] = batched_leg(ct, torch, dev)
+        if not args.no_batched:
+            res["batched"] = batched_leg(ct, torch, dev)
+            print("# batched leg done", file=sys.stderr, flush=True)
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(x_np, y_np, w_np, g_np, eps, args.cpu_iters)
+        res["cpu_baseline"] = cpu_baseline(x_np, y_np, w_np, eps, args.cpu_iters)
     print(json.dumps(res))
     return 0
+
+
+def parity_roofline_2d(out, x_np) -> dict:
+    """The headline step's gradient against the stored FP64 oracle pass over the
+    same inputs (tests/golden/roofline_2d_full.npz, written by the fixture script
+    from the oracle alone; it holds the cross and trajectory-self solves, so the
+    gradient with respect to the samples, not the value or weight gradient)."""
+    import numpy as np
+    f = os.path.join(ROOT, "tests", "golden", "roofline_2d_full.npz")
+    if not os.path.exists(f):
+        return {"tolerance": 1e-5, "reference": None}
+    F = np.load(f, allow_pickle=False)
+    return {"tolerance": 1e-5, "reference": "FP64 oracle, tests/golden/roofline_2d_full.npz",
+            "grad_x": rel_err(out[1].cpu().numpy(), F["grad_x"])}
+
+
+def grad_2d_leg(ct, torch, dev, L, _lib, tuned, steps: int = 20, warmup: int = 3,
+                graph: bool = False) -> dict:
+    """The 2-D gradient-field workload (T = 4096 random-walk samples, M = 16384
+    samples of a 5-component mixture, eps = 0.005, K = 200): S, dS/dx, dS/dw through
+    autograd (cross, self and reference-self solves) plus the Stein flow, on two
+    streams; its lagged sweeps' launch times from events in one more step; errors
+    against the stored FP64 oracle pass."""
+    import workloads as W
+    cfg = W.CONFIGS["grad_2d"]
+    T, M, d, eps, K = cfg.T, cfg.M, cfg.d, cfg.eps, cfg.iters
+    x_np, y_np, w_np, g_np = W.config_inputs(cfg)
+    x, y, w = (torch.as_tensor(a, device=dev) for a in (x_np, y_np, w_np))
+    gmm = ct.GMM.from_numpy(g_np, dev)
+    step = sinkhorn_step(ct, x, y, w, eps, K, gmm=gmm)
+    one = sinkhorn_step(ct, x, y, w, eps, K, gmm=gmm, one_stream=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        out = step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    graph_ms = None
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        gr = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr):
+            gout = step()
+        gr.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(steps):
+            gr.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        graph_ms = e0.elapsed_time(e1) / steps
+        assert torch.equal(gout[1], out[1])
+    L.ct_profile_clear()
+    L.ct_profile_enable(1)
+    one()
+    torch.cuda.synchronize()
+    L.ct_profile_enable(0)
+    dp, dms, nd = dominant_sweeps(read_profile(L, _lib))
+    pairs = pairs_per_pass(T, M, K) + T * T
+    ach = dp / (dms * 1e-3) / 1e12
+    peak = pair_roof(d, NOMINAL_RATES) / 1e12
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "sweep_traffic_grad_2d.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            rec = json.load(fh)
+        if rec.get("source_hash") == sweep_source_hash():
+            traffic = rec.get("bytes_per_launch")
+    return {"workload": f"grad_2d: d=2 T={T} M={M}, Sinkhorn eps={eps} K={K} debiased, S + "
+                        f"dS/dx + dS/dw via autograd (two streams), plus Stein flow",
+            "ms_per_step": ms, "pairs_per_step": pairs, "pair_evals_per_s": pairs / (ms * 1e-3),
+            "graph_ms_per_step": graph_ms, "schedules": tuned,
+            "sweep_launches": {"achieved": ach, "peak": peak, "unit": "Tpair/s",
+                               "frac": ach / peak, "launches": nd,
+                               "avg_launch_us": dms / max(nd, 1) * 1e3, "traffic": traffic,
+                               "events": "one extra step, launches serialised on one stream"},
+            "parity": parity_vs_stored_oracle(out, ct, torch, dev)}
 
 
 def horizon_sweep(ct, torch, dev) -> None:
@@ -317,7 +477,7 @@ def horizon_sweep(ct, torch, dev) -> None:
     import oracle
     import workloads as W
     cpu_limit = {"svgd_drive": 5000, "sinkhorn_aircraft": 2500}
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = omp_threads()
     for name, c in W.HORIZON_SWEEPS.items():
         warm = True
         for T in c["horizons"]:
@@ -395,7 +555,7 @@ def grid_leg(ct, torch, dev, reps: int = 20) -> None:
     import numpy as np
     import oracle
     import workloads as W
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = omp_threads()
 
     def timed(fn):
         fn()
@@ -577,8 +737,12 @@ def stein_leg(ct, torch, dev, L, _lib) -> dict:
                            "frac": None if ach is None else ach / peak, "pair_mix": STEIN_MIX}}
 
 
-def batched_leg(ct, torch, dev) -> dict:
-    """The 256-problem ragged batch: one persistent launch vs 256 plain calls."""
+def batched_leg(ct, torch, dev, reps: int = 3) -> dict:
+    """The 256-problem ragged batch (T_b in [500, 8000], M_b in [1024, 32768], eps =
+    0.01, K = 150, debiased gradient): the batched path (lockstep launches over job
+    tables, two sweep launches per iteration) run eagerly and as a captured HIP
+    graph replayed, against 256 plain calls; accuracy against the plain calls and
+    against the stored FP64 oracle passes of 16 of the problems."""
     import numpy as np
     import workloads as W
     cfg = W.CONFIGS["batched_2d"]
@@ -589,36 +753,49 @@ def batched_leg(ct, torch, dev) -> dict:
     bs = ct.BatchedSinkhorn(xs, ys, None, eps=eps, iters=K)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    bs.run()
-    torch.cuda.synchronize()
-    e0.record()
-    bs.run()
-    e1.record()
-    torch.cuda.synchronize()
-    t_b = e0.elapsed_time(e1)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_b = timed(bs.run)
+    eager = bs.grad_x.clone()
+    gr = bs.capture()
+    t_g = timed(gr.replay)
+    graph_equal = bool(torch.equal(bs.grad_x, eager))
     plain = [None] * len(probs)
 
     def run_plain():
         for b in range(len(probs)):
             plain[b] = ct.sinkhorn_grad(xs[b], ys[b], None, eps=eps, iters=K).grad_x
 
-    run_plain()
-    torch.cuda.synchronize()
-    e0.record()
-    run_plain()
-    e1.record()
-    torch.cuda.synchronize()
-    t_p = e0.elapsed_time(e1)
+    t_p = timed(run_plain)
     gx = bs.split(bs.grad_x, bs.T_off)
     err = max(float((gx[b] - plain[b]).norm() / plain[b].norm()) for b in range(len(probs)))
+    oracle_err = None
+    f = os.path.join(ROOT, "tests", "golden", "batched_2d_sample16.npz")
+    if os.path.exists(f):
+        F = np.load(f, allow_pickle=False)
+        off = np.concatenate([[0], np.cumsum(F["T"])])
+        oracle_err = max(rel_err(gx[int(b)].cpu().numpy(), F["grad_x"][off[i]:off[i + 1]])
+                         for i, b in enumerate(F["problems"]))
     pairs = sum(K * (2.0 * len(p[0]) * len(p[1]) + len(p[0]) ** 2) + len(p[0]) * len(p[1]) +
                 len(p[0]) ** 2 for p in probs)
     return {"workload": f"batched_2d: {len(probs)} problems, T in {cfg.extra['T_range']}, "
                         f"M in {cfg.extra['M_range']}, eps={eps}, K={K}, debiased grad_x",
-            "pairs": pairs, "batched_ms": t_b, "plain_ms": t_p, "speedup": t_p / t_b,
+            "pairs": pairs, "batched_ms": t_b, "graph_replay_ms": t_g, "plain_ms": t_p,
+            "speedup": t_p / t_b, "graph_speedup": t_p / t_g,
             "batched_pair_evals_per_s": pairs / (t_b * 1e-3),
             "plain_pair_evals_per_s": pairs / (t_p * 1e-3),
-            "max_rel_diff_batched_vs_plain": err}
+            "graph_replay_equals_eager": graph_equal,
+            "max_rel_diff_batched_vs_plain": err,
+            "max_rel_err_vs_oracle_16_problems": oracle_err}
 
 
 if __name__ == "__main__":

@@ -87,6 +87,46 @@ def svgd_phi(x, score, h: float) -> np.ndarray:
     return phi
 
 
+def _kth_sqdist(x, k: int, lo_bits: int = -1) -> float:
+    """The k-th smallest (0-based) squared distance |x_i - x_j|^2 over pairs i < j,
+    found by bisection on the threshold with pair counts: non-negative doubles
+    order like their bit patterns, so bisecting the pattern between one whose
+    count of pairs at or below it is <= k and one whose count exceeds k ends on
+    the exact value after at most 63 halvings."""
+    hi = 0x7FF0000000000000                       # +inf: every pair is at or below it
+    lo = lo_bits                                  # below every pair
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        v = float(np.array([mid], dtype=np.int64).view(np.float64)[0])
+        if pair_count(x, v)[1] >= k + 1:
+            hi = mid
+        else:
+            lo = mid
+    return float(np.array([hi], dtype=np.int64).view(np.float64)[0])
+
+
+def median_bandwidth_by_counting(x) -> float:
+    """The median heuristic of median_bandwidth, with the two middle order
+    statistics found by pair counting (no list of all n(n-1)/2 distances, so it
+    runs at any n); the same value in exact arithmetic and, as both take the
+    square root of the same double squared distance, in float64."""
+    x = f64(x)
+    n = x.shape[0]
+    if n < 2:
+        return 1.0
+    npair = n * (n - 1) // 2
+    k1, k2 = (npair - 1) // 2, npair // 2
+    v1 = _kth_sqdist(x, k1)
+    if k2 == k1 or pair_count(x, v1)[1] >= k2 + 1:
+        v2 = v1
+    else:
+        v2 = _kth_sqdist(x, k2, lo_bits=int(np.array([v1]).view(np.int64)[0]))
+    med = 0.5 * (np.sqrt(v1) + np.sqrt(v2))
+    if med == 0.0:
+        return 1.0
+    return float(med * med / np.log(n))
+
+
 def pair_count(x, thr_sq: float):
     """(#pairs i<j with |x_i-x_j|^2 < thr_sq, #pairs with <= thr_sq)."""
     x = f64(x)

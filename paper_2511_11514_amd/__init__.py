@@ -13,6 +13,6 @@ from .api import (sinkhorn_grad, sinkhorn_grad_batched, SinkhornDivergence, Batc
                   autotune_sinkhorn,
                   tuning_table, tuning_save, tuning_load, tuning_clear, GMM, version,
                   probe_alu_rates, svgd_grad_score, UtilityGrid, grid_score, grid_samples,
-                  static_scratch_bytes)
+                  reference_self_potential, static_scratch_bytes)
 
 __version__ = "0.1.0"

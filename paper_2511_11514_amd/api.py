@@ -122,18 +122,19 @@ def static_scratch_bytes() -> int:
 
 
 class SinkhornDivergence(torch.autograd.Function):
-    """S(x, (y, w)) as an autograd function (Sec. II-B, eq. 7 "through
-    auto-differentiation").  The forward pass computes S together with dS/dx and
+    """S(x, (y, w)) as an autograd function (Sec. II-B, eq. 7, by automatic
+    differentiation).  The forward pass computes S together with dS/dx and
     dS/dw (envelope theorem on the extrapolated potentials); the backward pass
     only scales them by the incoming gradient, so no second solve is needed."""
 
     @staticmethod
     def forward(ctx, x, y, w, eps: float, iters: int, debias: bool = True,
-                one_stream: bool = False):
+                one_stream: bool = False, ref_q: Optional[torch.Tensor] = None):
         need_w = bool(w is not None and ctx.needs_input_grad[2])
         out = sinkhorn_grad(x.detach(), y.detach(), None if w is None else w.detach(), eps=eps,
                             iters=iters, debias=debias, value=True, grad_w=need_w,
-                            one_stream=one_stream)
+                            one_stream=one_stream,
+                            ref_q=None if ref_q is None else ref_q.detach())
         ctx.save_for_backward(out.grad_x, out.grad_w if need_w else None)
         ctx.need_w = need_w
         return out.value.reshape(())
@@ -142,12 +143,28 @@ class SinkhornDivergence(torch.autograd.Function):
     @once_differentiable
     def backward(ctx, gS):
         gx, gw = ctx.saved_tensors
-        return gS * gx, None, (gS * gw if ctx.need_w else None), None, None, None, None
+        return gS * gx, None, (gS * gw if ctx.need_w else None), None, None, None, None, None
 
 
 def sinkhorn_divergence(x, y, w=None, *, eps: float, iters: int, debias: bool = True,
-                        one_stream: bool = False):
-    return SinkhornDivergence.apply(x, y, w, eps, iters, debias, one_stream)
+                        one_stream: bool = False, ref_q: Optional[torch.Tensor] = None):
+    """S(x, (y, w)) with autograd (SinkhornDivergence).  ref_q: the reference self
+    potential after the same `iters` averaged sweeps (reference_self_potential),
+    which does not depend on x: passing it skips those sweeps (CT_REF_CACHED) and
+    gives the result of recomputing it up to float32 rounding (the staged
+    coordinates are centred on the mean of the points of the call that made q)."""
+    return SinkhornDivergence.apply(x, y, w, eps, iters, debias, one_stream, ref_q)
+
+
+def reference_self_potential(y: torch.Tensor, w: Optional[torch.Tensor] = None, *, eps: float,
+                             iters: int) -> torch.Tensor:
+    """q after `iters` averaged sweeps q <- (q + T_b(q))/2 from zero: the reference
+    self problem OT(b, b) of eq. 6, independent of the trajectory, for reuse across
+    gradient calls with the same reference (ref_q).  Runs ct_sinkhorn_grad with a
+    single trajectory sample, so the cross and trajectory-self work is negligible."""
+    out = sinkhorn_grad(y[:1].contiguous(), y, w, eps=eps, iters=iters, value=True,
+                        potentials=True)
+    return out.pot[2 + y.shape[0]:].clone()   # pot = f[1], g[M], p[1], q[M]
 
 
 @dataclass

@@ -45,9 +45,13 @@ SINKHORN_NOREF = [
 BATCH = [
     ("batched_2d_sample16", list(range(0, 256, 16))),
 ]
+# (fixture name, workload, T, M of the draw that fixes the samples): M = 16 draws the
+# samples beside a 16-point reference; None takes the workload's own reference size,
+# i.e. the very samples its Sinkhorn workload uses (bandwidth by pair counting)
 STEIN = [
-    ("grad_2d_full_svgd", "grad_2d", None),
-    ("roofline_2d_T16384_svgd", "roofline_2d", 16384),
+    ("grad_2d_full_svgd", "grad_2d", None, 16),
+    ("roofline_2d_T16384_svgd", "roofline_2d", 16384, 16),
+    ("roofline_2d_full_svgd", "roofline_2d", None, None),
 ]
 
 
@@ -113,15 +117,15 @@ def batch_fixture(name, problems):
     print(f"{name}: {len(problems)} problems ({time.time() - t0:.0f} s)", flush=True)
 
 
-def stein_fixture(name, cfg_name, T):
+def stein_fixture(name, cfg_name, T, M):
     cfg = W.CONFIGS[cfg_name]
-    x, _y, _w, g = W.config_inputs(cfg, T=T, M=16)
+    x, _y, _w, g = W.config_inputs(cfg, T=T, M=M)
     t0 = time.time()
     sc = oracle.gmm_score(x, g.weights, g.means, g.sigmas, g.floor)
-    h = oracle.median_bandwidth(x)
+    h = oracle.median_bandwidth(x) if M is not None else oracle.median_bandwidth_by_counting(x)
     phi = oracle.svgd_phi(x, sc, h)
     np.savez_compressed(os.path.join(HERE, name + ".npz"), workload=cfg_name, T=len(x),
-                        score=sc, h=h, phi=phi)
+                        M_draw=-1 if M is None else M, score=sc, h=h, phi=phi)
     print(f"{name}: T={len(x)} h={h:.6g} ({time.time() - t0:.0f} s)", flush=True)
 
 

@@ -1,5 +1,5 @@
-"""The Sinkhorn divergence as a torch.autograd.Function (Sec. II-B, eq. 7 "through
-auto-differentiation"): backward w.r.t. samples and reference weights against
+"""The Sinkhorn divergence as a torch.autograd.Function (Sec. II-B, eq. 7, by automatic
+differentiation): backward w.r.t. samples and reference weights against
 the FP64 oracle gradient, against central differences of the converged oracle
 objective, and composition with other torch operations."""
 import numpy as np
@@ -81,3 +81,31 @@ def test_composes_with_torch_and_scales_with_grad_output(ct):
     x2 = torch.as_tensor(x, device=dev).requires_grad_(True)
     ct.sinkhorn_divergence(x2, yt, wt, eps=0.01, iters=30).backward()
     assert wt.grad is None and x2.grad is not None
+
+
+def test_cached_reference_potential_matches_recomputing_it(ct):
+    """The reference self potential does not depend on the trajectory (eq. 6's
+    OT(b, b)): computed once (reference_self_potential) and passed as ref_q, the
+    value and both gradients match a call that iterates it, within float32
+    rounding, and the FP64 oracle at 1e-5."""
+    dev = torch.device("cuda")
+    x, y, _w, _g = W.config_inputs(W.CONFIGS["roofline_2d"], T=1200, M=3001)
+    w = np.random.default_rng(7).uniform(0.5, 1.5, len(y)).astype(np.float32)
+    xt, yt, wt = (torch.as_tensor(a, device=dev) for a in (x, y, w))
+    eps, K = 0.01, 60
+    full = ct.sinkhorn_grad(xt, yt, wt, eps=eps, iters=K, value=True, grad_w=True)
+    q = ct.reference_self_potential(yt, wt, eps=eps, iters=K)
+    cached = ct.sinkhorn_grad(xt, yt, wt, eps=eps, iters=K, value=True, grad_w=True, ref_q=q)
+    xr = xt.clone().requires_grad_(True)
+    wr = wt.clone().requires_grad_(True)
+    S = ct.sinkhorn_divergence(xr, yt, wr, eps=eps, iters=K, ref_q=q)
+    S.backward()
+    torch.cuda.synchronize()
+    r = oracle.sinkhorn(x, y, w, eps=eps, iters=K)
+    assert rel(q.cpu().numpy(), r.q) < 1e-6
+    assert torch.equal(cached.grad_x, full.grad_x)          # q does not enter dS/dx
+    assert rel(cached.grad_w.cpu().numpy(), full.grad_w.cpu().numpy()) < 1e-6
+    assert abs(cached.value.item() - full.value.item()) <= 1e-6 * abs(full.value.item())
+    assert torch.equal(xr.grad, cached.grad_x) and torch.equal(wr.grad, cached.grad_w)
+    assert abs(S.item() - r.value) / abs(r.value) < 1e-5
+    assert rel(wr.grad.cpu().numpy(), r.grad_w) < 1e-5

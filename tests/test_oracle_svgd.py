@@ -107,3 +107,22 @@ def test_repulsion_is_antisymmetric_and_small_h_limit():
     att = oracle.svgd_phi(x, s, 0.2) - rep
     np.testing.assert_allclose(oracle.svgd_phi(x, 2 * s, 0.2), rep + 2 * att, atol=1e-13)
     assert np.isfinite(full).all()
+
+
+@pytest.mark.parametrize("case", ["uniform2", "uniform3", "lattice", "pair", "triple", "same"])
+def test_median_by_counting_equals_sorted_median(case):
+    """The pair-counting median (used where the distances cannot all be listed)
+    returns exactly the bandwidth of numpy.median over scipy's pdist, including
+    lattice points whose distances tie (even and odd pair counts), two and three
+    points, and coincident points (h = 1)."""
+    rng = np.random.default_rng(91)
+    x = {"uniform2": rng.uniform(size=(57, 2)), "uniform3": rng.uniform(size=(40, 3)),
+         "lattice": np.array(list(np.ndindex(5, 4)), dtype=np.float64) * 0.25,
+         "pair": rng.uniform(size=(2, 2)), "triple": rng.uniform(size=(3, 3)),
+         "same": np.ones((6, 2))}[case]
+    n = len(x)
+    med = float(np.median(pdist(x)))
+    ref = 1.0 if med == 0.0 else med * med / np.log(n)
+    got = oracle.median_bandwidth_by_counting(x)
+    assert got == oracle.median_bandwidth(x)
+    assert abs(got - ref) <= 1e-15 * ref
