@@ -10,7 +10,7 @@
  *                             (Sec. II-B, eqs. 5-7) w.r.t. the trajectory samples
  *                             and the reference weights, and its value;
  *   ct_status_sync            device-detected conditions of the last gradient call
- *                             (non-finite inputs, rescued rows);
+ *                             (non-finite inputs, rescued rows, convergence);
  *   ct_sinkhorn_grad_batched  the same for many independent problems of uneven
  *                             size (lockstep launches or one persistent kernel);
  *   ct_svgd_grad              Stein variational flow (Sec. II-B, eq. 4) with an
@@ -37,7 +37,9 @@
  * - GPU entry points are asynchronous on `stream` (a hipStream_t; NULL = the
  *   null stream): they enqueue kernels and return without synchronising, except
  *   ct_sinkhorn_batched_prepare, ct_grid_samples, ct_plan and ct_plan_ensemble,
- *   which are synchronous.  Two calls that share a workspace must be
+ *   which are synchronous.  Those, ct_status_sync, ct_autotune_sinkhorn and
+ *   ct_probe_alu_rates return CT_E_CAPTURE, enqueueing nothing, when `stream` is
+ *   being captured into a graph.  Two calls that share a workspace must be
  *   ordered on one stream.
  * - Arguments are validated on the host before anything is enqueued; an invalid
  *   call returns a negative status, enqueues nothing and leaves a message for
@@ -57,12 +59,16 @@ extern "C" {
 typedef int32_t ct_status;
 
 #define CT_OK 0
+#define CT_WARN_NOT_CONVERGED 1 /* ct_status_sync: column residual above the caller's tolerance */
 #define CT_E_ARG (-1)         /* null pointer, out-of-range scalar or bad flag */
 #define CT_E_SHAPE (-2)       /* sizes inconsistent or unsupported (d, T, M, B) */
+#define CT_E_NONFINITE (-3)   /* ct_status_sync: the device saw non-finite inputs or non-positive
+                                 weights, so the last call's outputs are not valid */
 #define CT_E_WORKSPACE (-4)   /* ws too small or misaligned */
 #define CT_E_HIP (-5)         /* a HIP runtime call failed (message has the HIP error) */
 #define CT_E_UNSUPPORTED (-6) /* feature not available for this input */
-#define CT_W_NONFINITE 1       /* ct_status_sync: the device saw non-finite inputs or non-positive weights */
+#define CT_E_CAPTURE (-7)     /* a synchronous entry point was called while its stream is being
+                                 captured into a graph (nothing was enqueued) */
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* ct_last_error(void);
@@ -172,16 +178,24 @@ ct_status ct_sinkhorn_grad_static(const float* x, int64_t T, const float* y, con
 /*
  * Status words that the last ct_sinkhorn_grad call on `ws` left in its workspace,
  * read after waiting for `stream` (the one synchronising query of the Sinkhorn
- * path; ct_sinkhorn_grad itself never waits).
+ * path; ct_sinkhorn_grad itself never waits).  The residual is the column
+ * marginal error of eq. 5's constraint for the plan of (f+, g),
+ * sum_j |sum_i pi_ij - b_j| (aux[3]); it is written only by calls with CT_VALUE
+ * or CT_GRAD_W (the pass that yields g+).
  *   ws         device, a workspace last used by ct_sinkhorn_grad (256-byte aligned)
+ *   resid_tol  tolerance of the residual, >= 0 (0: no convergence check)
  *   nonfinite  host [1] or NULL  out: non-finite input coordinates plus non-positive
  *              or non-finite weights (the count that aux[5] reports)
  *   rescued    host [1] or NULL  out: rows whose lagged shift was unusable and that
  *              were recomputed with a tracked maximum (aux[4])
- * Returns CT_W_NONFINITE (positive) when nonfinite > 0, else CT_OK; CT_E_ARG for a
- * null ws, CT_E_WORKSPACE for a misaligned one, CT_E_HIP.
+ *   resid      host [1] or NULL  out: the residual, NaN when the call computed none
+ * Returns CT_E_NONFINITE when nonfinite > 0; else CT_WARN_NOT_CONVERGED (positive)
+ * when resid_tol > 0 and a computed residual exceeds it (or is NaN); else CT_OK.
+ * CT_E_ARG for a null ws or a negative tolerance, CT_E_WORKSPACE for a misaligned
+ * ws, CT_E_CAPTURE while `stream` is being captured, CT_E_HIP.
  */
-ct_status ct_status_sync(const void* ws, uint32_t* nonfinite, uint32_t* rescued, void* stream);
+ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* nonfinite, uint32_t* rescued,
+                         float* resid, void* stream);
 
 /*
  * Many independent problems b = 0..B-1 of uneven size (the batched form of
@@ -201,8 +215,13 @@ ct_status ct_status_sync(const void* ws, uint32_t* nonfinite, uint32_t* rescued,
  * and copies it into `ws`; ct_sinkhorn_grad_batched itself only enqueues kernels
  * (no copies, no host synchronisation), so it may be captured into a graph and
  * replayed as long as the workspace stays prepared.  Returns CT_E_ARG for a
- * workspace not prepared for this batch.  A value of NaN signals that the
- * persistent kernel's bounded wait expired (an internal error, never expected).
+ * workspace not prepared for this batch.  If a wait of the persistent kernel on
+ * another problem's progress expires (an internal error, never expected: its
+ * work order guarantees progress, and the bound, 2^22 polls of about 0.1 us, only
+ * turns such an error into a result instead of a hang), every grad_x, grad_w and
+ * value entry of the call is NaN.  The environment variable
+ * CT_PERSISTENT_WAIT_POLLS, read at each call, replaces the bound (0: a wait
+ * expires at its first unsatisfied poll), to test that path.
  */
 size_t ct_sinkhorn_batched_workspace_size(int32_t B, const int64_t* T_off, const int64_t* M_off,
                                           const ct_sinkhorn_opts* o);
@@ -394,7 +413,7 @@ ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, const float* 
 
 /*
  * Seed ensemble.  Different initial controls reach different, equally good
- * optima of the planning problem (Sec. IV discussion), which several seeds can
+ * optima of the planning problem (Sec. III-C, the results), which several seeds can
  * exploit for robustness.  ct_plan_ensemble runs S planners that share the
  * problem p (dynamics, s0, T, dt), the options o and the reference samples, but
  * start from their own controls, in lockstep: every outer iteration rolls out

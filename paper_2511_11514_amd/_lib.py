@@ -13,12 +13,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libct.so")
 
 CT_OK = 0
+CT_WARN_NOT_CONVERGED = 1
 CT_E_ARG = -1
 CT_E_SHAPE = -2
+CT_E_NONFINITE = -3
 CT_E_WORKSPACE = -4
 CT_E_HIP = -5
 CT_E_UNSUPPORTED = -6
-CT_W_NONFINITE = 1
+CT_E_CAPTURE = -7
 
 CT_DEBIAS = 1
 CT_GRAD_W = 2
@@ -82,7 +84,8 @@ _SIGS = {
     "ct_sinkhorn_static_scratch_bytes": (c_size_t, []),
     "ct_sinkhorn_grad_static": (c_int32, [P, c_int64, P, P, c_int64, POINTER(SinkhornOpts), P, P,
                                           P, P, P, P, P]),
-    "ct_status_sync": (c_int32, [P, POINTER(c_uint32), POINTER(c_uint32), P]),
+    "ct_status_sync": (c_int32, [P, c_float, POINTER(c_uint32), POINTER(c_uint32),
+                                 POINTER(c_float), P]),
     "ct_sinkhorn_batched_workspace_size": (c_size_t, [c_int32, PI64, PI64, POINTER(SinkhornOpts)]),
     "ct_sinkhorn_batched_prepare": (c_int32, [c_int32, PI64, PI64, POINTER(SinkhornOpts), P,
                                               c_size_t, P]),

@@ -30,6 +30,7 @@
 // kernels, so it can be captured into a graph and replayed.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -259,6 +260,7 @@ struct BArgs {
     BLayout L;
     float kappa, inv_kappa, inv_sqrt_kappa;
     int safe_only;
+    unsigned wait_polls;   // polls of a dependency counter before the wait gives up
 };
 
 // Build the job of unit `local` of stage type `st` (0 A, 1 B, 2 F1, 3 F2) of problem P.
@@ -390,14 +392,16 @@ __global__ __launch_bounds__(kBlock) void k_bpersist(BArgs A) {
                                          (st == 3 ? P.nF1 : 0));
         if (threadIdx.x == 0) {
             // bounded wait: the dependency order guarantees progress; the bound only
-            // turns a logic error into a flagged (NaN-valued) result instead of a hang
+            // turns a logic error into a flagged result (every output NaN, the
+            // expiry reported by ct_sinkhorn_batched_status) instead of a hang
             unsigned spins = 0;
             while (__hip_atomic_load(&L.done[b], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins == (1u << 22)) {
+                if (spins >= A.wait_polls) {
                     atomicOr(L.counters + 2, 1u);
                     break;
                 }
+                __builtin_amdgcn_s_sleep(2);
+                ++spins;
             }
         }
         __syncthreads();
@@ -430,10 +434,13 @@ __global__ __launch_bounds__(256) void k_breduce(BLayout L, float kappa, float* 
     const BProb P = L.prob[blockIdx.x];
     const int d = H.d;
     const float two_a = 2.f / (float)P.T;
+    // a tripped wait bound (counters[2]) marks every output of every problem as invalid
+    const bool expired = L.counters[2] != 0u;
+    const float nan = __builtin_nanf("");
     for (int i = threadIdx.x; i < P.T * d; i += 256) {
         const size_t gi = (size_t)P.xo * d + i;
         const float v = H.debias ? L.ds[gi] - L.dy[gi] : -L.dy[gi];
-        grad_x[gi] = two_a * v;
+        grad_x[gi] = expired ? nan : two_a * v;
     }
     if (!value && !grad_w) return;
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -468,8 +475,7 @@ __global__ __launch_bounds__(256) void k_breduce(BLayout L, float kappa, float* 
         const double ot_ab = red[0][0] + red[3][0];
         const double S = H.debias ? ot_ab - 0.5 * (red[1][0] + red[2][0]) - 0.5 * (red[4][0] + red[5][0])
                                   : ot_ab;
-        // a tripped wait bound (counters[2]) marks every value as invalid
-        if (value) value[blockIdx.x] = L.counters[2] ? __builtin_nanf("") : (float)S;
+        if (value) value[blockIdx.x] = expired ? nan : (float)S;
         s_bG = red[6][0];
     }
     __syncthreads();
@@ -478,7 +484,7 @@ __global__ __launch_bounds__(256) void k_breduce(BLayout L, float kappa, float* 
         for (int j = threadIdx.x; j < P.M; j += 256) {
             const int gj = P.yo + j;
             const double G = H.need_ref ? (double)L.gp[gj] - (double)L.qp[gj] : (double)L.gp[gj];
-            grad_w[gj] = (float)((G - s_bG) / ws);
+            grad_w[gj] = expired ? nan : (float)((G - s_bG) / ws);
         }
     }
 }
@@ -713,6 +719,8 @@ extern "C" ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* To, c
     const size_t pf = lock_part_floats(B, To, Mo, o, S);
     BLayout L = b_layout(ws, B, S.sumT, S.sumM, S.sumTpad, S.sumMpad, o->d, pf);
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
+    rc = refuse_capture(static_cast<hipStream_t>(stream), "ct_sinkhorn_batched_prepare");
+    if (rc) return rc;
     const Schedule sc = batched_schedule(o->d);
     const int QB = 64 * sc.R * (4 / sc.WS);
     const bool debias = o->flags & CT_DEBIAS;
@@ -884,6 +892,8 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
     A.inv_kappa = (float)(1.0 / kappa_d);
     A.inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
     A.safe_only = (o->flags & CT_SAFE_LSE) ? 1 : 0;
+    A.wait_polls = 1u << 22;
+    if (const char* e = std::getenv("CT_PERSISTENT_WAIT_POLLS")) A.wait_polls = (unsigned)std::strtoul(e, nullptr, 10);
     const int grid = kNumCU * 4;
     void* tok = profile_begin(st);
 #define CT_BP(D, R, WS) hipLaunchKernelGGL((k_bpersist<D, R, WS>), dim3(grid), dim3(kBlock), 0, st, A)

@@ -18,6 +18,15 @@ ct_status fail(ct_status code, const char* fmt, ...) {
 
 void clear_error() { g_msg[0] = '\0'; }
 
+ct_status refuse_capture(hipStream_t st, const char* what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    CT_CHECK_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(CT_E_CAPTURE, "%s synchronises with the device and cannot run while its "
+                                  "stream is being captured", what);
+    return CT_OK;
+}
+
 }  // namespace ct
 
 extern "C" const char* ct_last_error(void) { return ct::g_msg; }

@@ -13,6 +13,8 @@ namespace ct {
 // ---------------------------------------------------------------- errors
 ct_status fail(ct_status code, const char* fmt, ...);
 void clear_error();
+// CT_E_CAPTURE (with a message naming `what`) if `st` is being captured into a graph.
+ct_status refuse_capture(hipStream_t st, const char* what);
 
 #define CT_CHECK_HIP(call)                                                                  \
     do {                                                                                    \

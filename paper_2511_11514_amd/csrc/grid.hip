@@ -306,6 +306,8 @@ extern "C" ct_status ct_grid_samples(const ct_grid* g, int32_t d, float* y, floa
     SampleLayout L = sample_layout(ws, N);
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = refuse_capture(st, "ct_grid_samples");
+    if (rc) return rc;
     const GridDev G = grid_dev(g, d);
     const int nb = (int)((N + kGridBlock - 1) / kGridBlock);
     hipLaunchKernelGGL(k_grid_count, dim3(nb), dim3(kGridBlock), 0, st, G, N, L.W);

@@ -338,6 +338,8 @@ extern "C" ct_status ct_plan(const ct_plan_problem* p, const ct_plan_opts* o, co
     PlanLayout L = plan_layout(ws, p, o, M);
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
     hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = refuse_capture(st, "ct_plan");
+    if (rc) return rc;
     const int64_t T = p->T;
     const int d = D.d, n = D.n, m = D.m;
     std::vector<double> traj((size_t)(T + 1) * n), A((size_t)T * n * n), B((size_t)T * n * m);
@@ -507,6 +509,8 @@ extern "C" ct_status ct_plan_ensemble(const ct_plan_problem* p, const ct_plan_op
     if (!u || !value || !best) return fail(CT_E_ARG, "u, value and best must be non-null");
     if (!ws) return fail(CT_E_ARG, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
+    rc = refuse_capture(static_cast<hipStream_t>(stream), "ct_plan_ensemble");
+    if (rc) return rc;
     const int64_t T = p->T;
     if ((int64_t)S * T > (int64_t(1) << 30) || (int64_t)S * M > (int64_t(1) << 30))
         return fail(CT_E_SHAPE, "S*T and S*M must be <= 2^30");

@@ -19,6 +19,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // kind 0: v_add_f32, 1: v_fma_f32, 2: v_exp_f32, 3: v_mfma_f32_16x16x4f32 (4 chains),
 // 4: the MFMA chains and the exp chains of kinds 2 and 3 in the same waves.
+// The addend c is formed by a vector multiply, so the add chain compiles to
+// v_add_f32 with two vector-register operands (the form of the sweep's pair loop, whose adds
+// have no scalar operand); adds with a scalar-register operand issue at about
+// half that rate on gfx950.
 template <int KIND>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rate(
     float* __restrict__ out, float seed) {
@@ -88,9 +92,10 @@ extern "C" ct_status ct_probe_alu_rates(double* out6, void* ws, size_t ws_bytes,
         return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes,
                     ct_probe_workspace_size());
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    CT_CHECK_HIP(hipStreamIsCapturing(st, &cs));
-    if (cs != hipStreamCaptureStatusNone) return fail(CT_E_ARG, "cannot probe while capturing");
+    {
+        const ct_status rc = refuse_capture(st, "ct_probe_alu_rates");
+        if (rc) return rc;
+    }
     int dev = 0, khz = 0, ncu = 0;
     CT_CHECK_HIP(hipGetDevice(&dev));
     CT_CHECK_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeClockRate, dev));

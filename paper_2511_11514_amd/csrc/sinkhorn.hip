@@ -186,7 +186,8 @@ struct ReduceArgs {
     const float* qp;
     const float* b;
     const double* wsum;
-    const unsigned* counters;   // [0] non-finite inputs, [1] rescued rows
+    unsigned* counters;         // [0] non-finite inputs, [1] rescued rows, [2] residual (float
+                                // bits), [3] 1 once the residual is written
     double* bG;                 // out: <b, G>
     float* value;
     float* aux;
@@ -235,6 +236,8 @@ __global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
             A.aux[2] = A.need_ref ? (float)ot_bb : 0.f;
             A.aux[3] = (float)red[7][0];
         }
+        A.counters[2] = __float_as_uint((float)red[7][0]);
+        A.counters[3] = 1u;
     }
 }
 
@@ -801,9 +804,8 @@ extern "C" ct_status ct_autotune_sinkhorn(int64_t T64, int64_t M64, const ct_sin
     SkLayout L = sk_layout(ws, T, M, d);
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    CT_CHECK_HIP(hipStreamIsCapturing(st, &cs));
-    if (cs != hipStreamCaptureStatusNone) return fail(CT_E_ARG, "cannot autotune while capturing");
+    rc = refuse_capture(st, "ct_autotune_sinkhorn");
+    if (rc) return rc;
     const double kappa_d = kLog2e / (double)o->eps;
     const int n = std::max(pad_keys(T), pad_keys(M));
     hipLaunchKernelGGL(k_zero3, dim3(((int)L.ntick + 255) / 256), dim3(256), 0, st, L.tick[0],
@@ -861,21 +863,34 @@ extern "C" ct_status ct_autotune_sinkhorn(int64_t T64, int64_t M64, const ct_sin
     return CT_OK;
 }
 
-extern "C" ct_status ct_status_sync(const void* ws, uint32_t* nonfinite, uint32_t* rescued,
-                                    void* stream) {
+extern "C" ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* nonfinite,
+                                    uint32_t* rescued, float* resid, void* stream) {
     clear_error();
     if (!ws) return fail(CT_E_ARG, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(CT_E_WORKSPACE, "workspace not 256-byte aligned");
+    if (!(resid_tol >= 0.f)) return fail(CT_E_ARG, "resid_tol must be >= 0 (0: no convergence check)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ct_status rc = refuse_capture(st, "ct_status_sync");
+    if (rc) return rc;
     // the counters come before every size-dependent buffer of the layout; a stand-in
     // base (never dereferenced) gives their offset
     char* const probe = reinterpret_cast<char*>(uintptr_t(1) << 20);
     const size_t off = static_cast<size_t>(reinterpret_cast<char*>(sk_layout(probe, 1, 1, 2).counters) - probe);
-    unsigned c[2] = {0u, 0u};
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned c[4] = {0u, 0u, 0u, 0u};
     CT_CHECK_HIP(hipMemcpyAsync(c, static_cast<const char*>(ws) + off, sizeof(c),
                                 hipMemcpyDeviceToHost, st));
     CT_CHECK_HIP(hipStreamSynchronize(st));
+    float r;
+    std::memcpy(&r, &c[2], sizeof(r));
+    if (!c[3]) r = __builtin_nanf("");
     if (nonfinite) *nonfinite = c[0];
     if (rescued) *rescued = c[1];
-    return c[0] ? CT_W_NONFINITE : CT_OK;
+    if (resid) *resid = r;
+    if (c[0])
+        return fail(CT_E_NONFINITE, "the last gradient call saw %u non-finite coordinates or "
+                                    "non-positive weights: its outputs are not valid", c[0]);
+    if (resid_tol > 0.f && c[3] && !(r <= resid_tol))
+        return fail(CT_WARN_NOT_CONVERGED, "column residual %.3g above the tolerance %.3g", r,
+                    resid_tol);
+    return CT_OK;
 }

@@ -16,6 +16,12 @@ CT_FIXTURE_CHECKPOINT (a directory, default the system's temporary one), so
 an interrupted run resumes where it stopped; the chunks continue the same
 iteration exactly (the oracle's warm start), so the result does not depend on
 the chunking.
+
+The Stein fixture of the large workload takes the samples of its Sinkhorn
+inputs (T = 65536) and the bandwidth from the pair-counting median (the sorted
+median would list 2.1e9 distances).  The finite-difference fixture holds the
+converged FP64 gradients of a 3-D instance (T = 2048, M = 8192) and central
+differences of its converged objective on 64 sample coordinates and 64 weights.
 """
 import os
 import sys
@@ -48,6 +54,10 @@ BATCH = [
 # (fixture name, workload, T, M of the draw that fixes the samples): M = 16 draws the
 # samples beside a 16-point reference; None takes the workload's own reference size,
 # i.e. the very samples its Sinkhorn workload uses (bandwidth by pair counting)
+# (fixture name, workload, T, M): central differences of the converged objective
+FD = [
+    ("fd_3d_T2048_M8192", "autograd_3d", 2048, 8192),
+]
 STEIN = [
     ("grad_2d_full_svgd", "grad_2d", None, 16),
     ("roofline_2d_T16384_svgd", "roofline_2d", 16384, 16),
@@ -117,6 +127,50 @@ def batch_fixture(name, problems):
     print(f"{name}: {len(problems)} problems ({time.time() - t0:.0f} s)", flush=True)
 
 
+def _converged(x, y, w, eps, init, tol=1e-13):
+    r = oracle.sinkhorn(x, y, w, eps=eps, iters=25, init=init)
+    while r.resid > tol:
+        r = oracle.sinkhorn(x, y, w, eps=eps, iters=25, init=(r.f, r.g, r.p, r.q))
+    return r
+
+
+def fd_fixture(name, cfg_name, T, M):
+    """The converged FP64 gradients (column residual below 1e-13) and central
+    differences of the converged objective (h from the workload, each side
+    re-solved from the converged potentials) on the workload's number of seeded
+    random coordinates of the samples and of the reference weights (weights drawn
+    in [0.5, 2])."""
+    cfg = W.CONFIGS[cfg_name]
+    x, y, _w, _g = W.config_inputs(cfg, T=T, M=M)
+    w = W.positive_weights(np.random.default_rng(1), M)
+    xd, yd, wd = (a.astype(np.float64) for a in (x, y, w))
+    eps, h, n = cfg.eps, cfg.extra["fd_h"], cfg.extra["fd_coords"]
+    t0 = time.time()
+    base = _converged(xd, yd, wd, eps, None)
+    init = (base.f, base.g, base.p, base.q)
+    rng = np.random.default_rng(cfg.seed + 7)
+    xi = rng.choice(T * cfg.d, n, replace=False)
+    wj = rng.choice(M, n, replace=False)
+    fdx, fdw = np.empty(n), np.empty(n)
+    for c, flat in enumerate(xi):
+        i, k = divmod(int(flat), cfg.d)
+        xp, xm = xd.copy(), xd.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        fdx[c] = (_converged(xp, yd, wd, eps, init).value -
+                  _converged(xm, yd, wd, eps, init).value) / (2 * h)
+    for c, j in enumerate(wj):
+        wp, wm = wd.copy(), wd.copy()
+        wp[j] += h
+        wm[j] -= h
+        fdw[c] = (_converged(xd, yd, wp, eps, init).value -
+                  _converged(xd, yd, wm, eps, init).value) / (2 * h)
+    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload=cfg_name, T=T, M=M, eps=eps,
+                        h=h, w=w, grad_x=base.grad_x, grad_w=base.grad_w, value=base.value,
+                        resid=base.resid, x_coords=xi, w_coords=wj, fd_x=fdx, fd_w=fdw)
+    print(f"{name}: T={T} M={M} {n}+{n} coordinates ({time.time() - t0:.0f} s)", flush=True)
+
+
 def stein_fixture(name, cfg_name, T, M):
     cfg = W.CONFIGS[cfg_name]
     x, _y, _w, g = W.config_inputs(cfg, T=T, M=M)
@@ -137,6 +191,9 @@ if __name__ == "__main__":
     for spec in SINKHORN:
         if not want or spec[0] in want:
             sinkhorn_fixture(*spec)
+    for spec in FD:
+        if not want or spec[0] in want:
+            fd_fixture(*spec)
     for spec in BATCH:
         if not want or spec[0] in want:
             batch_fixture(*spec)

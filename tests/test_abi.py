@@ -222,8 +222,23 @@ def test_svgd_score_and_grid_plan_reject_bad_arguments_before_launch():
 def test_status_sync_rejects_bad_workspaces():
     from paper_2511_11514_amd import _lib
     L = _lib.lib()
-    assert L.ct_status_sync(None, None, None, None) == _lib.CT_E_ARG
-    assert L.ct_status_sync(ctypes.c_void_p(257), None, None, None) == _lib.CT_E_WORKSPACE
+    assert L.ct_status_sync(None, 0.0, None, None, None, None) == _lib.CT_E_ARG
+    assert L.ct_status_sync(ctypes.c_void_p(257), 0.0, None, None, None, None) == \
+        _lib.CT_E_WORKSPACE
+    assert L.ct_status_sync(ctypes.c_void_p(256), -1.0, None, None, None, None) == _lib.CT_E_ARG
+
+
+def test_status_codes_match_the_header():
+    """The binding's status constants are the header's."""
+    import re
+    from paper_2511_11514_amd import _lib
+    src = open(os.path.join(ROOT, "include", "ct.h")).read()
+    codes = dict(re.findall(r"#define (CT_(?:OK|WARN_[A-Z_]+|E_[A-Z_]+)) \(?(-?\d+)\)?", src))
+    assert set(codes) >= {"CT_OK", "CT_WARN_NOT_CONVERGED", "CT_E_ARG", "CT_E_SHAPE",
+                          "CT_E_NONFINITE", "CT_E_WORKSPACE", "CT_E_HIP", "CT_E_UNSUPPORTED",
+                          "CT_E_CAPTURE"}
+    for name, v in codes.items():
+        assert getattr(_lib, name) == int(v), name
 
 
 def test_static_scratch_entry_rejects_before_launch():

@@ -158,3 +158,26 @@ def test_lockstep_edge_cases(ct, iters, debias, safe):
         assert np.abs(gx[b] - r.grad_x).max() <= TOL * scale + 1e-7, b
         assert rel(gw[b], r.grad_w) < TOL or np.abs(gw[b] - r.grad_w).max() < 1e-6, b
         assert abs(val[b] - r.value) <= TOL * abs(r.value) + 1e-7, b
+
+
+def test_expired_persistent_wait_flags_every_output(ct, monkeypatch):
+    """The persistent kernel's dependency waits are bounded; when one expires (forced
+    here from the host: a bound of zero polls, so every wait that is not satisfied
+    at once gives up and the kernel still runs to its end), every gradient and
+    value of the call is NaN; with the normal bound the same prepared batch gives
+    the oracle's results again."""
+    probs = _ragged(77, 3, 3000, 5000)
+    eps, iters = 0.01, 8
+    bs = _batch(ct, probs, eps, iters, persistent=True)
+    monkeypatch.setenv("CT_PERSISTENT_WAIT_POLLS", "0")
+    bs.run()
+    torch.cuda.synchronize()
+    assert torch.isnan(bs.grad_x).all() and torch.isnan(bs.grad_w).all()
+    assert torch.isnan(bs.value).all()
+    monkeypatch.delenv("CT_PERSISTENT_WAIT_POLLS")
+    bs.run()
+    torch.cuda.synchronize()
+    gx = bs.split(bs.grad_x, bs.T_off)
+    for b, (x, y, w) in enumerate(probs):
+        r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
+        assert rel(gx[b].cpu().numpy(), r.grad_x) < TOL

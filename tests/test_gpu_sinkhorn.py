@@ -214,9 +214,11 @@ def test_one_stream_and_two_streams_agree(ct):
 
 
 def test_status_sync_reports_device_detected_conditions(ct):
-    """ct_status_sync reads the workspace's status words: OK and the rescued-row
-    count for clean inputs; CT_W_NONFINITE and the count for NaN coordinates and a
-    zero weight, matching aux[5]."""
+    """ct_status_sync reads the workspace's status words: OK with the rescued-row
+    count and the column residual for clean inputs (the residual equals aux[3]
+    and the oracle's); CT_WARN_NOT_CONVERGED when that residual is above the
+    caller's tolerance; CT_E_NONFINITE and the count for NaN coordinates and a zero
+    weight, matching aux[5]; a NaN residual for a call that computes none."""
     from paper_2511_11514_amd import _lib
     import ctypes
     L = _lib.lib()
@@ -228,6 +230,7 @@ def test_status_sync_reports_device_detected_conditions(ct):
     ws = torch.empty(nb, dtype=torch.uint8, device=dev)
     P = lambda z: ctypes.c_void_p(z.data_ptr())
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    r = oracle.sinkhorn(x, y, w, eps=0.01, iters=20)
     for bad in (False, True):
         xb, wb = x.copy(), w.copy()
         if bad:
@@ -241,14 +244,51 @@ def test_status_sync_reports_device_detected_conditions(ct):
         st = L.ct_sinkhorn_grad(P(xt), T, P(yt), P(wt), M, ctypes.byref(o), P(gx), None, P(val),
                                 None, None, P(aux), P(ws), nb, stream)
         assert st == 0
-        nf, rs = ctypes.c_uint32(), ctypes.c_uint32()
-        s = L.ct_status_sync(P(ws), ctypes.byref(nf), ctypes.byref(rs), stream)
+        nf, rs, res = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_float()
+        s = L.ct_status_sync(P(ws), 0.0, ctypes.byref(nf), ctypes.byref(rs), ctypes.byref(res),
+                             stream)
         a = aux.cpu().numpy()
         assert nf.value == int(a[5]) and rs.value == int(a[4])
         if bad:
-            assert s == _lib.CT_W_NONFINITE and nf.value == 3
+            assert s == _lib.CT_E_NONFINITE and nf.value == 3
+            assert b"non-finite" in L.ct_last_error()
         else:
             assert s == _lib.CT_OK and nf.value == 0
+            assert res.value == a[3] and abs(res.value - r.resid) <= 1e-3 * r.resid
+            tight = L.ct_status_sync(P(ws), 0.5 * res.value, None, None, None, stream)
+            assert tight == _lib.CT_WARN_NOT_CONVERGED
+            assert L.ct_status_sync(P(ws), 2.0 * res.value, None, None, None, stream) == 0
+    # gradient only: no residual is computed, so no convergence warning either
+    o2 = _lib.SinkhornOpts(d, 20, 0.01, _lib.CT_DEBIAS)
+    xt, yt = torch.as_tensor(x, device=dev), torch.as_tensor(y, device=dev)
+    assert L.ct_sinkhorn_grad(P(xt), T, P(yt), None, M, ctypes.byref(o2), P(gx), None, None,
+                              None, None, None, P(ws), nb, stream) == 0
+    res = ctypes.c_float()
+    assert L.ct_status_sync(P(ws), 1e-30, None, None, ctypes.byref(res), stream) == 0
+    assert np.isnan(res.value)
+
+
+def test_synchronous_entry_points_refuse_capture(ct):
+    """While the stream is being captured, the synchronous calls return
+    CT_E_CAPTURE and enqueue nothing, so the capture stays valid."""
+    from paper_2511_11514_amd import _lib
+    import ctypes
+    L = _lib.lib()
+    dev = torch.device("cuda")
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device=dev)
+    a = torch.ones(16, device=dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        st = L.ct_status_sync(ctypes.c_void_p(ws.data_ptr()), 0.0, None, None, None, stream)
+        o = _lib.SinkhornOpts(2, 1, 0.01, _lib.CT_DEBIAS)
+        st2 = L.ct_autotune_sinkhorn(64, 64, ctypes.byref(o), ctypes.c_void_p(ws.data_ptr()),
+                                     1 << 20, stream)
+        a.mul_(2.0)
+    assert st == _lib.CT_E_CAPTURE and st2 == _lib.CT_E_CAPTURE
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.all(a == 2.0)          # one replay of the captured multiply
 
 
 @pytest.mark.parametrize("d,T,M", [(2, 3000, 5000), (3, 1500, 2600)])
