@@ -15,7 +15,9 @@ or weight gradient.  Its iterations run in chunks whose state is kept in
 CT_FIXTURE_CHECKPOINT (a directory, default the system's temporary one), so
 an interrupted run resumes where it stopped; the chunks continue the same
 iteration exactly (the oracle's warm start), so the result does not depend on
-the chunking.
+the chunking.  CT_FIXTURE_MAX_SECONDS stops such a run after the chunk that
+passes that many seconds (the checkpoint stays for the next run), and
+CT_FIXTURE_DIR writes the fixtures to another directory than this one.
 
 The Stein fixture of the large workload takes the samples of its Sinkhorn
 inputs (T = 65536) and the bandwidth from the pair-counting median (the sorted
@@ -31,6 +33,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+OUT = os.environ.get("CT_FIXTURE_DIR", HERE)
 
 import oracle  # noqa: E402
 import workloads as W  # noqa: E402
@@ -71,7 +74,7 @@ def sinkhorn_fixture(name, cfg_name, T, M, iters):
     K = cfg.iters if iters is None else iters
     t0 = time.time()
     r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=K)
-    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload=cfg_name, T=len(x), M=len(y),
+    np.savez_compressed(os.path.join(OUT, name + ".npz"), workload=cfg_name, T=len(x), M=len(y),
                         eps=cfg.eps, iters=K, grad_x=r.grad_x, grad_w=r.grad_w, value=r.value,
                         f=r.f, g=r.g, p=r.p, q=r.q, f_plus=r.f_plus, g_plus=r.g_plus,
                         resid=r.resid)
@@ -92,8 +95,13 @@ def sinkhorn_noref_fixture(name, cfg_name, chunk=25):
         f, g, p, done = c["f"], c["g"], c["p"], int(c["done"])
         print(f"{name}: resuming after {done} iterations", flush=True)
     t0 = time.time()
+    limit = float(os.environ.get("CT_FIXTURE_MAX_SECONDS", "inf"))
     zq = np.zeros(M)
     while done < K:
+        if time.time() - t0 > limit:
+            print(f"{name}: stopping after {done}/{K} iterations (time limit); checkpoint {ck}",
+                  flush=True)
+            return
         n = min(chunk, K - done)
         r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=n, want_value=False, want_grad_w=False,
                             init=(f, g, p, zq))
@@ -103,7 +111,7 @@ def sinkhorn_noref_fixture(name, cfg_name, chunk=25):
         print(f"{name}: {done}/{K} iterations ({time.time() - t0:.0f} s)", flush=True)
     r = oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=0, want_value=False, want_grad_w=False,
                         init=(f, g, p, zq))
-    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload=cfg_name, T=T, M=M,
+    np.savez_compressed(os.path.join(OUT, name + ".npz"), workload=cfg_name, T=T, M=M,
                         eps=cfg.eps, iters=K, grad_x=r.grad_x, f=r.f, g=r.g, p=r.p,
                         f_plus=r.f_plus, p_plus=r.p_plus)
     print(f"{name}: T={T} M={M} K={K} ({time.time() - t0:.0f} s)", flush=True)
@@ -121,7 +129,7 @@ def batch_fixture(name, problems):
         Ts.append(len(x))
         Ms.append(len(y))
         grads.append(r.grad_x)
-    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload="batched_2d",
+    np.savez_compressed(os.path.join(OUT, name + ".npz"), workload="batched_2d",
                         problems=np.array(problems), T=np.array(Ts), M=np.array(Ms),
                         eps=cfg.eps, iters=cfg.iters, grad_x=np.concatenate(grads))
     print(f"{name}: {len(problems)} problems ({time.time() - t0:.0f} s)", flush=True)
@@ -165,7 +173,7 @@ def fd_fixture(name, cfg_name, T, M):
         wm[j] -= h
         fdw[c] = (_converged(xd, yd, wp, eps, init).value -
                   _converged(xd, yd, wm, eps, init).value) / (2 * h)
-    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload=cfg_name, T=T, M=M, eps=eps,
+    np.savez_compressed(os.path.join(OUT, name + ".npz"), workload=cfg_name, T=T, M=M, eps=eps,
                         h=h, w=w, grad_x=base.grad_x, grad_w=base.grad_w, value=base.value,
                         resid=base.resid, x_coords=xi, w_coords=wj, fd_x=fdx, fd_w=fdw)
     print(f"{name}: T={T} M={M} {n}+{n} coordinates ({time.time() - t0:.0f} s)", flush=True)
@@ -178,7 +186,7 @@ def stein_fixture(name, cfg_name, T, M):
     sc = oracle.gmm_score(x, g.weights, g.means, g.sigmas, g.floor)
     h = oracle.median_bandwidth(x) if M is not None else oracle.median_bandwidth_by_counting(x)
     phi = oracle.svgd_phi(x, sc, h)
-    np.savez_compressed(os.path.join(HERE, name + ".npz"), workload=cfg_name, T=len(x),
+    np.savez_compressed(os.path.join(OUT, name + ".npz"), workload=cfg_name, T=len(x),
                         M_draw=-1 if M is None else M, score=sc, h=h, phi=phi)
     print(f"{name}: T={len(x)} h={h:.6g} ({time.time() - t0:.0f} s)", flush=True)
 
