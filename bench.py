@@ -208,6 +208,9 @@ def main() -> int:
     ap.add_argument("--grad-2d-only", action="store_true",
                     help="instead of the benchmark line: only the 2-D gradient-field leg "
                          "(T = 4096, M = 16384), for profiling its launches")
+    ap.add_argument("--stein-only", action="store_true",
+                    help="instead of the benchmark line: only the Stein leg (T = 65536), for "
+                         "profiling its median and sum kernels")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -246,6 +249,9 @@ def main() -> int:
         tuned = None
     else:
         ct.tuning_load(table)
+    if args.stein_only:
+        print(json.dumps(stein_leg(ct, torch, dev, L, _lib)))
+        return 0
     if args.grad_2d_only:
         print(json.dumps(grad_2d_leg(ct, torch, dev, L, _lib, tuned, steps=args.steps,
                                      warmup=args.warmup, graph=args.graph)))
@@ -467,6 +473,36 @@ def grad_2d_leg(ct, torch, dev, L, _lib, tuned, steps: int = 20, warmup: int = 3
             "parity": parity_vs_stored_oracle(out, ct, torch, dev)}
 
 
+def planner_2d_row(ct, torch, dev, reps: int = 3) -> None:
+    """The 2-D planner workload (double integrator, T = 256, M = 512, eps = 0.01,
+    K = 100, ten outer iterations, step 0.5): ct_plan wall time per outer
+    iteration with the library's default execution (the fused solve at this size)
+    and with one launch per sweep, best of `reps` runs after a warm-up call."""
+    import numpy as np
+    import workloads as W
+    cfg = W.CONFIGS["planner_2d"]
+    e = cfg.extra
+    _x, y, w, _g = W.config_inputs(cfg)
+    u0 = np.random.default_rng(cfg.seed + 1).normal(size=(cfg.T, 2)) * e["u_std"]
+    s0 = np.array(e["s0"])
+    Q, R = e["Q"] * np.eye(2), e["R"] * np.eye(2)
+    kw = dict(y=torch.as_tensor(y, device=dev), w=torch.as_tensor(w, device=dev), eps=cfg.eps,
+              iters=cfg.iters)
+    row = {"workload": "planner_2d", "T": cfg.T, "M": cfg.M, "K": cfg.iters, "outer": e["outer"]}
+    for key, fused in (("default", None), ("unfused", False)):
+        ct.plan(e["dynamics"], s0, u0, e["dt"], Q, R, "sinkhorn", 1, 0.5, fused=fused, **kw)
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            _u, _s, hist = ct.plan(e["dynamics"], s0, u0, e["dt"], Q, R, "sinkhorn", e["outer"],
+                                   0.5, fused=fused, **kw)
+            best = min(best, time.perf_counter() - t0)
+        row[f"ms_per_outer_{key}"] = 1e3 * best / e["outer"]
+        row[f"objective_{key}"] = [float(hist[0]), float(hist[-1])]
+    row["unfused_over_default"] = row["ms_per_outer_unfused"] / row["ms_per_outer_default"]
+    print(json.dumps(row), flush=True)
+
+
 def horizon_sweep(ct, torch, dev) -> None:
     """Planner wall time against the horizon T: the Stein flow with differential
     drive and the Sinkhorn flow with the 3-D point mass (stand-in for the paper's
@@ -478,6 +514,7 @@ def horizon_sweep(ct, torch, dev) -> None:
     import workloads as W
     cpu_limit = {"svgd_drive": 5000, "sinkhorn_aircraft": 2500}
     threads = omp_threads()
+    planner_2d_row(ct, torch, dev)
     for name, c in W.HORIZON_SWEEPS.items():
         warm = True
         for T in c["horizons"]:
@@ -500,6 +537,17 @@ def horizon_sweep(ct, torch, dev) -> None:
                    "M": None if y is None else len(y), "outer": c["outer"], "gpu_s": gpu,
                    "gpu_s_per_outer": gpu / c["outer"], "first_objective": float(hist[0]),
                    "last_objective": float(hist[-1])}
+            if c["flow"] == "sinkhorn":
+                # the same planner with one launch per sweep (no fused solve)
+                ct.plan(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"], 1, c["step"],
+                        fused=False, **kw)
+                t0 = time.perf_counter()
+                _u2, _s2, hist2 = ct.plan(c["dynamics"], s0, u0, c["dt"], Q, R, c["flow"],
+                                          c["outer"], c["step"], fused=False, **kw)
+                gpu2 = time.perf_counter() - t0
+                row.update({"gpu_s_per_outer_unfused": gpu2 / c["outer"],
+                            "unfused_over_default": gpu2 / gpu,
+                            "last_objective_unfused": float(hist2[-1])})
             if T <= cpu_limit[name]:
                 if warm or T <= 1000:
                     # untimed call first: the oracle's first call loads its C library, and

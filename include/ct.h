@@ -69,6 +69,9 @@ typedef int32_t ct_status;
 #define CT_E_UNSUPPORTED (-6) /* feature not available for this input */
 #define CT_E_CAPTURE (-7)     /* a synchronous entry point was called while its stream is being
                                  captured into a graph (nothing was enqueued) */
+#define CT_E_DEVICE (-8)      /* ct_status_sync: a bounded wait inside a kernel (the grid barrier
+                                 of the fused solve) gave up, so the last call's outputs are not
+                                 valid (they are NaN) */
 
 /* Message of the last failing call on this thread ("" if none). */
 const char* ct_last_error(void);
@@ -92,6 +95,20 @@ const char* ct_version(void);
                              cross sweeps; the fork/join is graph-capture compatible) */
 #define CT_PERSISTENT 128u /* batched path only: one persistent launch walking a dependency-
                             ordered work list instead of lockstep launches per iteration */
+#define CT_FUSED 256u   /* run all K iterations in one launch of co-resident blocks with a
+                           grid-wide barrier after each half-iteration (f and p, then g and q),
+                           instead of one launch per sweep; meant for small problems (short
+                           horizons), whose per-iteration launches are bound by launch latency.
+                           Without CT_FUSED or CT_UNFUSED the library picks the fused solve
+                           when one iteration has few enough point pairs. */
+#define CT_UNFUSED 512u /* never use the fused solve (one launch per sweep) */
+#define CT_EXPANDED 1024u /* per-sweep launches: evaluate the lagged sweeps' exponent in the
+                             expanded form around a per-wave origin, h_j - |k'|^2 + 2 q'.k'
+                             - |q'|^2 - shift (d FMAs and one add per pair instead of d
+                             subtractions, d FMAs and one subtraction); the extrapolation pass,
+                             the first (tracked-maximum) sweep and rescued rows keep the
+                             difference form.  Its rounding grows with the spread of the
+                             queries a wave holds. */
 
 typedef struct ct_sinkhorn_opts {
     int32_t d;      /* 2 or 3 */
@@ -138,9 +155,11 @@ size_t ct_sinkhorn_workspace_size(int64_t T, int64_t M, const ct_sinkhorn_opts* 
  *                               CT_GRAD_W, else 0), [4] number of rows whose lagged
  *                               shift was unusable and that were recomputed with a
  *                               tracked maximum, [5] number of non-finite inputs or
- *                               non-positive weights, [6], [7] zero
+ *                               non-positive weights, [6] 1 if a grid barrier of
+ *                               the fused solve gave up (outputs NaN), [7] zero
  * Errors: CT_E_ARG (null x/y/grad_x/ws, eps <= 0 or non-finite, iters < 0, grad_w
- * without CT_GRAD_W, pot missing for CT_WARM_START/CT_REF_CACHED, unknown flag),
+ * without CT_GRAD_W, pot missing for CT_WARM_START/CT_REF_CACHED, unknown flag,
+ * CT_FUSED together with CT_UNFUSED),
  * CT_E_SHAPE (d not 2/3, T < 1, M < 1, T or M > 2^30), CT_E_WORKSPACE, CT_E_HIP.
  */
 ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const float* w, int64_t M,
@@ -189,7 +208,8 @@ ct_status ct_sinkhorn_grad_static(const float* x, int64_t T, const float* y, con
  *   rescued    host [1] or NULL  out: rows whose lagged shift was unusable and that
  *              were recomputed with a tracked maximum (aux[4])
  *   resid      host [1] or NULL  out: the residual, NaN when the call computed none
- * Returns CT_E_NONFINITE when nonfinite > 0; else CT_WARN_NOT_CONVERGED (positive)
+ * Returns CT_E_DEVICE when a grid barrier of the fused solve gave up (its outputs
+ * are NaN); else CT_E_NONFINITE when nonfinite > 0; else CT_WARN_NOT_CONVERGED (positive)
  * when resid_tol > 0 and a computed residual exceeds it (or is NaN); else CT_OK.
  * CT_E_ARG for a null ws or a negative tolerance, CT_E_WORKSPACE for a misaligned
  * ws, CT_E_CAPTURE while `stream` is being captured, CT_E_HIP.

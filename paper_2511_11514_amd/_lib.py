@@ -21,6 +21,7 @@ CT_E_WORKSPACE = -4
 CT_E_HIP = -5
 CT_E_UNSUPPORTED = -6
 CT_E_CAPTURE = -7
+CT_E_DEVICE = -8
 
 CT_DEBIAS = 1
 CT_GRAD_W = 2
@@ -30,6 +31,9 @@ CT_REF_CACHED = 16
 CT_SAFE_LSE = 32
 CT_ONE_STREAM = 64
 CT_PERSISTENT = 128
+CT_FUSED = 256
+CT_UNFUSED = 512
+CT_EXPANDED = 1024
 
 CT_DYN_DOUBLE_INTEGRATOR = 0
 CT_DYN_UNICYCLE = 1

@@ -62,17 +62,25 @@ def _opts(d: int, eps: float, iters: int, flags: int) -> L.SinkhornOpts:
     return L.SinkhornOpts(int(d), int(iters), float(eps), int(flags))
 
 
+def _fused_flag(fused: Optional[bool]) -> int:
+    return 0 if fused is None else (L.CT_FUSED if fused else L.CT_UNFUSED)
+
+
 def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = None, *,
                   eps: float, iters: int, debias: bool = True, value: bool = False,
                   grad_w: bool = False, init: Optional[torch.Tensor] = None,
                   ref_q: Optional[torch.Tensor] = None, safe: bool = False,
                   potentials: bool = False, aux: bool = False,
-                  one_stream: bool = False, static_scratch: bool = False) -> SinkhornOut:
+                  one_stream: bool = False, static_scratch: bool = False,
+                  fused: Optional[bool] = None, expanded: bool = False) -> SinkhornOut:
     """Gradient of the (debiased) Sinkhorn divergence; see ct_sinkhorn_grad.
 
     x [T,d], y [M,d], w [M] or None: float32 GPU tensors.
     init: optional [2T+2M] starting potentials (f, g, p, q) -> CT_WARM_START.
     ref_q: optional [M] converged reference self potential -> CT_REF_CACHED.
+    fused: True -> CT_FUSED (all iterations in one launch), False -> CT_UNFUSED,
+    None -> the library's size rule.
+    expanded: CT_EXPANDED (the lagged sweeps' exponent in the expanded form).
     static_scratch: call ct_sinkhorn_grad_static (the library's static device
     scratch instead of a workspace; only the outputs are allocated here).
     """
@@ -87,7 +95,8 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
         raise ValueError("x and y must have the same dimension")
     flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
         (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
-        (L.CT_ONE_STREAM if one_stream else 0)
+        (L.CT_ONE_STREAM if one_stream else 0) | _fused_flag(fused) | \
+        (L.CT_EXPANDED if expanded else 0)
     pot = None
     if init is not None or ref_q is not None or potentials:
         pot = torch.zeros(2 * T + 2 * M, dtype=torch.float32, device=dev)
@@ -129,12 +138,13 @@ class SinkhornDivergence(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, y, w, eps: float, iters: int, debias: bool = True,
-                one_stream: bool = False, ref_q: Optional[torch.Tensor] = None):
+                one_stream: bool = False, ref_q: Optional[torch.Tensor] = None,
+                expanded: bool = False):
         need_w = bool(w is not None and ctx.needs_input_grad[2])
         out = sinkhorn_grad(x.detach(), y.detach(), None if w is None else w.detach(), eps=eps,
                             iters=iters, debias=debias, value=True, grad_w=need_w,
                             one_stream=one_stream,
-                            ref_q=None if ref_q is None else ref_q.detach())
+                            ref_q=None if ref_q is None else ref_q.detach(), expanded=expanded)
         ctx.save_for_backward(out.grad_x, out.grad_w if need_w else None)
         ctx.need_w = need_w
         return out.value.reshape(())
@@ -143,17 +153,20 @@ class SinkhornDivergence(torch.autograd.Function):
     @once_differentiable
     def backward(ctx, gS):
         gx, gw = ctx.saved_tensors
-        return gS * gx, None, (gS * gw if ctx.need_w else None), None, None, None, None, None
+        return (gS * gx, None, (gS * gw if ctx.need_w else None), None, None, None, None, None,
+                None)
 
 
 def sinkhorn_divergence(x, y, w=None, *, eps: float, iters: int, debias: bool = True,
-                        one_stream: bool = False, ref_q: Optional[torch.Tensor] = None):
+                        one_stream: bool = False, ref_q: Optional[torch.Tensor] = None,
+                        expanded: bool = False):
     """S(x, (y, w)) with autograd (SinkhornDivergence).  ref_q: the reference self
     potential after the same `iters` averaged sweeps (reference_self_potential),
     which does not depend on x: passing it skips those sweeps (CT_REF_CACHED) and
     gives the result of recomputing it up to float32 rounding (the staged
-    coordinates are centred on the mean of the points of the call that made q)."""
-    return SinkhornDivergence.apply(x, y, w, eps, iters, debias, one_stream, ref_q)
+    coordinates are centred on the mean of the points of the call that made q).
+    expanded: CT_EXPANDED (the lagged sweeps' exponent in the expanded form)."""
+    return SinkhornDivergence.apply(x, y, w, eps, iters, debias, one_stream, ref_q, expanded)
 
 
 def reference_self_potential(y: torch.Tensor, w: Optional[torch.Tensor] = None, *, eps: float,
@@ -414,9 +427,11 @@ _FLOW = {"sinkhorn": L.CT_FLOW_SINKHORN, "svgd": L.CT_FLOW_SVGD, "svgd_grid": L.
 def plan(dynamics: str, s0, u, dt: float, Q, R, flow: str, outer: int, step: float = 1.0, *,
          y: Optional[torch.Tensor] = None, w: Optional[torch.Tensor] = None,
          gmm: Optional[GMM] = None, grid: Optional[UtilityGrid] = None, eps: float = 0.01,
-         iters: int = 100, debias: bool = True, svgd_h: float = 0.0, device=None):
+         iters: int = 100, debias: bool = True, svgd_h: float = 0.0, device=None,
+         fused: Optional[bool] = None):
     """Outer planning loop (ct_plan).  flow: "sinkhorn" (y, w), "svgd" (gmm) or
-    "svgd_grid" (grid).  Returns (u [T,m], s [T+1,n], hist [outer])."""
+    "svgd_grid" (grid).  fused: as for sinkhorn_grad.  Returns (u [T,m],
+    s [T+1,n], hist [outer])."""
     s0 = _f64(s0)
     u = _f64(u).copy()
     Q = _f64(Q)
@@ -427,7 +442,7 @@ def plan(dynamics: str, s0, u, dt: float, Q, R, flow: str, outer: int, step: flo
     dev = torch.device(device) if device is not None else (
         y.device if y is not None else gmm.weights.device if gmm is not None else grid.u.device)
     prob = L.PlanProblem(_DYN[dynamics], d, T, float(dt), _dp(s0))
-    sk = _opts(d, eps, iters, L.CT_DEBIAS if debias else 0)
+    sk = _opts(d, eps, iters, (L.CT_DEBIAS if debias else 0) | _fused_flag(fused))
     gdesc = grid.desc() if grid is not None else None
     opts = L.PlanOpts(_FLOW[flow], int(outer), float(step), _dp(Q), _dp(R), sk, float(svgd_h),
                       ctypes.pointer(gdesc) if gdesc is not None else None)

@@ -104,6 +104,7 @@ struct BLayout {
     unsigned* head;         // [1] next unit
     unsigned* counters;     // [4]
     double* wsum;           // [B]
+    float* origin;          // [B][4] per-problem origin subtracted before scaling
     float4 *cx, *cy;        // query coordinates
     float4* xrec[4];        // as in the plain path, per problem at offset xp
     float4* yrec[3];
@@ -136,6 +137,7 @@ static BLayout b_layout(void* ws, int B, int64_t sumT, int64_t sumM, int64_t sum
     L.head = a.take<unsigned>(1);
     L.counters = a.take<unsigned>(4);
     L.wsum = a.take<double>(B);
+    L.origin = a.take<float>((size_t)B * 4);
     L.cx = a.take<float4>(sumT);
     L.cy = a.take<float4>(sumM);
     for (int r = 0; r < 4; ++r) L.xrec[r] = a.take<float4>(sumTpad);
@@ -168,23 +170,46 @@ __device__ __forceinline__ int find_prob(const int* off, int B, int e) {
     return lo;
 }
 
-__global__ __launch_bounds__(256) void k_bwsum(BLayout L, const float* __restrict__ w) {
-    __shared__ double red[256];
+// One block per problem: the sum of its reference weights and the common origin
+// of its points (mean of every finite coordinate of its T + M points), both in
+// double, fixed order.  The origin plays the part it plays in the single-problem
+// path: subtracted before the float32 prescale by sqrt(kappa), so points far
+// from the coordinate origin keep the low bits of their differences.
+__global__ __launch_bounds__(256) void k_bwsum(BLayout L, const float* __restrict__ x,
+                                               const float* __restrict__ y,
+                                               const float* __restrict__ w, int d) {
+    __shared__ double red[5][256];
     const BProb P = L.prob[blockIdx.x];
-    double s = 0.0;
+    double s = 0.0, c[3] = {0.0, 0.0, 0.0}, n = 0.0;
     if (w) {
         for (int j = threadIdx.x; j < P.M; j += 256) s += (double)w[P.yo + j];
     } else {
         s = threadIdx.x == 0 ? (double)P.M : 0.0;
     }
-    red[threadIdx.x] = s;
+    for (int i = threadIdx.x; i < P.T + P.M; i += 256) {
+        const float* pt = i < P.T ? x + (size_t)(P.xo + i) * d : y + (size_t)(P.yo + i - P.T) * d;
+        bool ok = true;
+        for (int t = 0; t < d; ++t) ok = ok && isfinite(pt[t]);
+        if (!ok) continue;
+        for (int t = 0; t < d; ++t) c[t] += (double)pt[t];
+        n += 1.0;
+    }
+    red[0][threadIdx.x] = s;
+    for (int t = 0; t < 3; ++t) red[1 + t][threadIdx.x] = c[t];
+    red[4][threadIdx.x] = n;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 5; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x < 4) {
+        const double cnt = red[4][0] > 0.0 ? red[4][0] : 1.0;
+        L.origin[(size_t)blockIdx.x * 4 + threadIdx.x] =
+            (int)threadIdx.x < d ? (float)(red[1 + threadIdx.x][0] / cnt) : 0.f;
+    }
     if (threadIdx.x == 0) {
-        L.wsum[blockIdx.x] = red[0];
+        L.wsum[blockIdx.x] = red[0][0];
         L.done[blockIdx.x] = 0u;
         if (blockIdx.x == 0) {
             *L.head = 0u;
@@ -212,7 +237,8 @@ __global__ __launch_bounds__(256) void k_bstage(BLayout L, const float* __restri
         float c[3] = {0.f, 0.f, 0.f};
         if (i < P.T) {
             const int gi = P.xo + i;
-            for (int t = 0; t < d; ++t) c[t] = x[(size_t)gi * d + t] * sqrt_kappa;
+            for (int t = 0; t < d; ++t)
+                c[t] = (x[(size_t)gi * d + t] - L.origin[(size_t)b * 4 + t]) * sqrt_kappa;
             L.cx[gi] = make_float4(c[0], c[1], c[2], 0.f);
             L.f[gi] = 0.f;
             L.p[gi] = 0.f;
@@ -233,7 +259,8 @@ __global__ __launch_bounds__(256) void k_bstage(BLayout L, const float* __restri
         float c[3] = {0.f, 0.f, 0.f};
         if (j < P.M) {
             const int gj = P.yo + j;
-            for (int t = 0; t < d; ++t) c[t] = y[(size_t)gj * d + t] * sqrt_kappa;
+            for (int t = 0; t < d; ++t)
+                c[t] = (y[(size_t)gj * d + t] - L.origin[(size_t)b * 4 + t]) * sqrt_kappa;
             L.cy[gj] = make_float4(c[0], c[1], c[2], 0.f);
             const float wj = w ? w[gj] : 1.f;
             if (!(wj > 0.f) || !isfinite(wj)) atomicAdd(L.counters, 1u);
@@ -840,7 +867,7 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double kappa_d = kLog2e / (double)o->eps;
-    hipLaunchKernelGGL(k_bwsum, dim3(B), dim3(256), 0, st, L, w);
+    hipLaunchKernelGGL(k_bwsum, dim3(B), dim3(256), 0, st, L, x, y, w, o->d);
     CT_CHECK_HIP(hipGetLastError());
     const int64_t n = std::max(S.sumTpad, S.sumMpad);
     hipLaunchKernelGGL(k_bstage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, L, x, y, w,

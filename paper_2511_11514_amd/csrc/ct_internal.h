@@ -79,6 +79,7 @@ struct Launch {
     Job job[kMaxJobs];
     int blk_end[kMaxJobs]; // job j owns blocks [blk_end[j-1], blk_end[j])
     int njobs;
+    int expanded;          // 1: lagged sweeps without offsets use the expanded pair form
     float kappa, inv_kappa, inv_sqrt_kappa;
 };
 
@@ -122,6 +123,47 @@ int plan_job_target(Job& j, const Schedule& s, double pairs_per_block);
 // Sweep kernel (separate-merge mode) then, if any job is split, the merge kernel.
 hipError_t launch_tab(int d, const Schedule& sc, bool lagged, bool bary, const TabLaunch& L,
                       hipStream_t s);
+
+// Fused solve of one small problem: all K iterations in one launch of co-resident
+// blocks, a grid-wide barrier after each half-iteration.  Half-iteration 0 holds
+// the f update and the trajectory self update p, half-iteration 1 the g update and
+// the reference self update q (the self chains are independent of the cross one,
+// so each rides in the half that balances the work).  The self jobs swap their
+// ping-pong record arrays every iteration, hence one job set per parity.
+struct FusedPhase {
+    Job job[2];
+    int unit_end[2];       // job j owns units [unit_end[j-1], unit_end[j])
+    int njobs;             // 1 or 2
+};
+struct FusedLaunch {
+    FusedPhase ph[2][2];   // [iteration parity][half]
+    int iters;
+    int lagged0;           // 1: the first iteration already has a usable shift (warm start)
+    int safe_only;         // 1: every sweep tracks its maximum
+    unsigned* bar;         // [kFusedBarWords] barrier words (zero at launch): per group of
+                           // kFusedGroup blocks an arrival count and a release word, one
+                           // arrival count of the groups; each on its own 128-byte line
+    unsigned* expired;     // set when a barrier wait gave up (zero at launch)
+    unsigned wait_polls;   // polls of the arrival counter before a wait gives up
+    unsigned target_extra; // 0; 1 makes every wait unsatisfiable (tests of the give-up path)
+    float kappa, inv_kappa, inv_sqrt_kappa;
+};
+// Schedule of the fused kernel: R = 1 query per lane, the keys split across the
+// four waves of a block (64 queries per block).
+constexpr int kFusedR = 1;
+constexpr int kFusedWS = 4;
+// Barrier layout: blocks form groups of kFusedGroup; a block arrives at its group's
+// counter, the group's last arrival at the top counter, and the groups' last arrivals
+// release their groups.  At most kFusedMaxGrid blocks.
+constexpr int kFusedGroup = 16;
+constexpr int kFusedMaxGrid = 2048;
+constexpr int kFusedMaxGroups = kFusedMaxGrid / kFusedGroup;
+constexpr int kFusedLine = 32;   // words per counter (one 128-byte line each)
+constexpr int kFusedBarWords = (2 * kFusedMaxGroups + 1) * kFusedLine;
+// Blocks of the fused kernel that can be resident at once on the current device
+// (0 if the occupancy query fails).
+int fused_resident_blocks(int d);
+hipError_t launch_fused(int d, const FusedLaunch& L, int nblocks, hipStream_t s);
 
 // Per-launch event timing (ct_profile_enable); no-ops when disabled.
 bool profiling();

@@ -2,6 +2,7 @@
 // (Sec. II-B, eqs. 5-7).  Staging, the iteration schedule, the final
 // extrapolation pass and the reductions; the sweeps themselves are in sweep.hip.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -163,14 +164,16 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs A) {
     }
 }
 
-// grad_x = 2 a (Ds - Dy)  (debiased) or -2 a Dy.
+// grad_x = 2 a (Ds - Dy)  (debiased) or -2 a Dy; NaN after a barrier of the fused
+// solve gave up (*expired).
 __global__ __launch_bounds__(256) void k_grad_x(const float* __restrict__ dy,
                                                 const float* __restrict__ ds, int n, float two_a,
+                                                const unsigned* __restrict__ expired,
                                                 float* __restrict__ out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float v = ds ? ds[i] - dy[i] : -dy[i];
-    out[i] = two_a * v;
+    out[i] = *expired ? __builtin_nanf("") : two_a * v;
 }
 
 struct ReduceArgs {
@@ -187,7 +190,8 @@ struct ReduceArgs {
     const float* b;
     const double* wsum;
     unsigned* counters;         // [0] non-finite inputs, [1] rescued rows, [2] residual (float
-                                // bits), [3] 1 once the residual is written
+                                // bits), [3] 1 once the residual is written, [4] a barrier of
+                                // the fused solve gave up
     double* bG;                 // out: <b, G>
     float* value;
     float* aux;
@@ -229,7 +233,7 @@ __global__ __launch_bounds__(1024) void k_reduce(ReduceArgs A) {
         const double ot_bb = red[4][0] + red[5][0];
         const double S = A.debias ? ot_ab - 0.5 * ot_aa - 0.5 * ot_bb : ot_ab;
         *A.bG = red[6][0];
-        if (A.value) *A.value = (float)S;
+        if (A.value) *A.value = A.counters[4] ? __builtin_nanf("") : (float)S;
         if (A.aux) {
             A.aux[0] = (float)ot_ab;
             A.aux[1] = A.debias ? (float)ot_aa : 0.f;
@@ -245,18 +249,19 @@ __global__ __launch_bounds__(256) void k_grad_w(const float* __restrict__ gp,
                                                 const float* __restrict__ qp, int M,
                                                 const double* __restrict__ bG,
                                                 const double* __restrict__ wsum,
+                                                const unsigned* __restrict__ expired,
                                                 float* __restrict__ out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= M) return;
     const double G = qp ? (double)gp[j] - (double)qp[j] : (double)gp[j];
-    out[j] = (float)((G - *bG) / *wsum);
+    out[j] = *expired ? __builtin_nanf("") : (float)((G - *bG) / *wsum);
 }
 
 __global__ void k_counters_out(const unsigned* __restrict__ c, float* __restrict__ aux) {
     if (threadIdx.x == 0) {
         aux[4] = (float)c[1];
         aux[5] = (float)c[0];
-        aux[6] = 0.f;
+        aux[6] = c[4] ? 1.f : 0.f;
         aux[7] = 0.f;
     }
 }
@@ -266,7 +271,7 @@ __global__ void k_counters_out(const unsigned* __restrict__ c, float* __restrict
 struct SkLayout {
     double* wsum;
     double* bG;
-    unsigned* counters;      // [4]
+    unsigned* counters;      // [8]: see ReduceArgs
     float4* cx;
     float4* cy;
     float4* xrec[4];         // 0: h from f (keys of g-sweeps), 1: from f+, 2/3: from p (ping-pong)
@@ -280,8 +285,11 @@ struct SkLayout {
     float* part[3];          // partial buffers: cross jobs, x self jobs, y self jobs
     unsigned* tick[3];
     size_t ntick;
+    unsigned* bar;           // [kFusedBarWords] barrier words of the fused solve
     size_t bytes;
 };
+
+constexpr int kCounters = 8;
 
 static SkLayout sk_layout(void* ws, int T, int M, int d) {
     Arena a(ws);
@@ -289,7 +297,7 @@ static SkLayout sk_layout(void* ws, int T, int M, int d) {
     const int Tp = pad_keys(T), Mp = pad_keys(M);
     L.wsum = a.take<double>(1);
     L.bG = a.take<double>(1);
-    L.counters = a.take<unsigned>(4);
+    L.counters = a.take<unsigned>(kCounters);
     L.cx = a.take<float4>(T);
     L.cy = a.take<float4>(M);
     for (int r = 0; r < 4; ++r) L.xrec[r] = a.take<float4>(Tp);
@@ -312,12 +320,14 @@ static SkLayout sk_layout(void* ws, int T, int M, int d) {
     L.part[2] = a.take<float>(job_part_floats_max(d, M, M));
     L.ntick = std::max(job_tickets_max(T), job_tickets_max(M));
     for (int i = 0; i < 3; ++i) L.tick[i] = a.take<unsigned>(L.ntick);
+    L.bar = a.take<unsigned>(kFusedBarWords);
     L.bytes = a.off + 256;
     return L;
 }
 
 static const uint32_t kKnownFlags = CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_WARM_START |
-                                    CT_REF_CACHED | CT_SAFE_LSE | CT_ONE_STREAM;
+                                    CT_REF_CACHED | CT_SAFE_LSE | CT_ONE_STREAM | CT_FUSED |
+                                    CT_UNFUSED | CT_EXPANDED;
 
 static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
                           const ct_sinkhorn_opts* o) {
@@ -331,6 +341,8 @@ static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
         return fail(CT_E_ARG, "eps must be finite and > 0");
     if (o->iters < 0) return fail(CT_E_ARG, "iters must be >= 0");
     if (o->flags & ~kKnownFlags) return fail(CT_E_ARG, "unknown flag bits 0x%x", o->flags & ~kKnownFlags);
+    if ((o->flags & CT_FUSED) && (o->flags & CT_UNFUSED))
+        return fail(CT_E_ARG, "CT_FUSED and CT_UNFUSED exclude each other");
     if (!x || !y) return fail(CT_E_ARG, "x and y must be non-null");
     return CT_OK;
 }
@@ -338,6 +350,7 @@ static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
 // Launch-time constants of one problem.
 struct SkConsts {
     int d, T, M;
+    int expanded;   // CT_EXPANDED: lagged sweeps without offsets in the expanded form
     float kappa, inv_kappa, inv_sqrt_kappa, log2a;
 };
 
@@ -347,6 +360,7 @@ static SkConsts sk_consts(int T, int M, const ct_sinkhorn_opts* o) {
     c.d = o->d;
     c.T = T;
     c.M = M;
+    c.expanded = (o->flags & CT_EXPANDED) ? 1 : 0;
     c.kappa = (float)kappa_d;
     c.inv_kappa = (float)(1.0 / kappa_d);
     c.inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
@@ -370,6 +384,7 @@ static ct_status launch_set(const JobSet& js, const SkConsts& c, const Schedule&
     Lc.kappa = c.kappa;
     Lc.inv_kappa = c.inv_kappa;
     Lc.inv_sqrt_kappa = c.inv_sqrt_kappa;
+    Lc.expanded = c.expanded;
     int nb = 0;
     for (int i = 0; i < js.n; ++i) {
         Lc.job[i] = js.j[i];
@@ -451,6 +466,96 @@ struct ForkJoin {
     hipEvent_t fork = nullptr, join = nullptr;
 };
 
+// Fused solve (all K iterations in one launch; see fused.hip).  By default it is
+// taken when one iteration has at most kFusedAutoPairs point pairs: there the
+// per-sweep launches are bound by launch latency, and two grid barriers per
+// iteration cost less than the four or five kernel boundaries they replace
+// (measured on an MI355X: 1.1-1.4x at 100-500 samples per side; from about 10^6
+// pairs per iteration on, the barriers' cross-die cache write-backs cost more
+// than the launches).  CT_FUSED forces it and CT_UNFUSED rules it out.  The grid
+// has at most kFusedMaxBlocks blocks and never more than can be resident at once.
+constexpr double kFusedAutoPairs = 524288.0;
+constexpr int kFusedMaxBlocks = 512;
+constexpr unsigned kFusedWaitPolls = 1u << 20;
+
+static ct_status run_fused(const SkLayout& L, const SkConsts& c, const SkJobs& J,
+                           const ct_sinkhorn_opts* o, bool debias, bool ref_iter, bool warm,
+                           bool safe_only, hipStream_t st, bool* ran) {
+    *ran = false;
+    const int T = c.T, M = c.M, d = c.d;
+    const bool forced = o->flags & CT_FUSED;
+    const double pa = (double)T * M + (debias ? (double)T * T : 0.0);
+    const double pb = (double)M * T + (ref_iter ? (double)M * M : 0.0);
+    if (!forced && pa + pb > kFusedAutoPairs) return CT_OK;
+    int gmax = std::min(fused_resident_blocks(d), kFusedMaxBlocks);
+    // test and tuning hook: a cap on the grid
+    if (const char* e = std::getenv("CT_FUSED_GRID"))
+        gmax = std::min(std::min(fused_resident_blocks(d), kFusedMaxGrid),
+                        std::max(1, std::atoi(e)));
+    if (gmax < 1) {
+        if (forced) return fail(CT_E_UNSUPPORTED, "the fused solve cannot place a block on this device");
+        return CT_OK;
+    }
+    // partial buffers of the layout: cross jobs, trajectory self, reference self
+    const size_t cap_cross = std::max(job_part_floats_max(d, T, M), job_part_floats_max(d, M, T));
+    const size_t cap_p = job_part_floats_max(d, T, T), cap_q = job_part_floats_max(d, M, M);
+    const Schedule fs{kFusedR, kFusedWS, 0, 0};
+    FusedLaunch F;
+    std::memset(&F, 0, sizeof(F));
+    // plan every job for about the same pairs per unit, so that one half-iteration
+    // is about one unit per block; coarser units if a job's partials would not fit
+    double ppb = std::max(pa, pb) / gmax;
+    int units_max = 0;
+    for (int attempt = 0;; ++attempt) {
+        bool fits = true;
+        units_max = 0;
+        auto add = [&](FusedPhase& P, Job j, size_t cap) {
+            const int u = plan_job_target(j, fs, ppb);
+            const size_t need = j.splits > 1 ? (size_t)(2 + d) * j.splits * (size_t)j.nqb * 64 *
+                                                   kFusedR * (4 / kFusedWS)
+                                             : 0;
+            if (need > cap) fits = false;
+            P.job[P.njobs] = j;
+            P.unit_end[P.njobs] = (P.njobs ? P.unit_end[P.njobs - 1] : 0) + u;
+            ++P.njobs;
+            units_max = std::max(units_max, P.unit_end[P.njobs - 1]);
+        };
+        for (int par = 0; par < 2; ++par) {
+            FusedPhase& A = F.ph[par][0];
+            FusedPhase& B = F.ph[par][1];
+            A.njobs = B.njobs = 0;
+            add(A, J.f(L.f, L.xrec[0], nullptr), cap_cross);
+            if (debias) add(A, J.p(par, true, L.p, L.xrec[2 + (par ^ 1)], nullptr), cap_p);
+            add(B, J.g(L.xrec[0], L.g, L.yrec[0]), cap_cross);
+            if (ref_iter) add(B, J.q(par, true, L.q, L.yrec[1 + (par ^ 1)]), cap_q);
+        }
+        if (fits) break;
+        if (attempt >= 30) {
+            if (forced) return fail(CT_E_UNSUPPORTED, "the fused solve found no plan for T=%d, M=%d", T, M);
+            return CT_OK;
+        }
+        ppb *= 2.0;
+    }
+    F.iters = o->iters;
+    F.lagged0 = warm ? 1 : 0;
+    F.safe_only = safe_only ? 1 : 0;
+    F.bar = L.bar;
+    F.expired = L.counters + 4;
+    F.wait_polls = kFusedWaitPolls;
+    // test hooks of the give-up path: a poll bound, and waits that no arrival count satisfies
+    if (const char* e = std::getenv("CT_FUSED_WAIT_POLLS")) F.wait_polls = (unsigned)std::strtoul(e, nullptr, 10);
+    if (const char* e = std::getenv("CT_FUSED_UNSATISFIABLE_WAITS")) F.target_extra = std::atoi(e) ? 1u : 0u;
+    F.kappa = c.kappa;
+    F.inv_kappa = c.inv_kappa;
+    F.inv_sqrt_kappa = c.inv_sqrt_kappa;
+    hipLaunchKernelGGL(k_zero3, dim3((kFusedBarWords + 255) / 256), dim3(256), 0, st, L.bar,
+                       kFusedBarWords, nullptr, 0, nullptr, 0);
+    CT_CHECK_HIP(hipGetLastError());
+    CT_CHECK_HIP(launch_fused(d, F, std::min(gmax, units_max), st));
+    *ran = true;
+    return CT_OK;
+}
+
 // Iterate-and-extrapolate for one problem whose arrays are staged in L.
 static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_opts* o,
                              hipStream_t st, const ForkJoin* fj) {
@@ -466,11 +571,19 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     const Schedule sA = schedule_for(d, T, M);
     const Schedule sB = schedule_for(d, M, T);
 
+    int cur = 0;  // which ping-pong self record array is current
+    bool fused = false;
+    if (o->iters > 0 && !(o->flags & CT_UNFUSED)) {
+        ct_status rc = run_fused(L, c, J, o, debias, ref_iter, warm, safe_only, st, &fused);
+        if (rc) return rc;
+        if (fused) cur = o->iters & 1;
+    }
+
     // The self problems do not depend on f and g: their K sweeps run on the
     // auxiliary stream (forked from / joined back into `st` with events) while the
     // cross sweeps run on `st`; with CT_ONE_STREAM the same launches are serialised
     // on `st`.
-    const bool any_self = debias || ref_iter;
+    const bool any_self = !fused && (debias || ref_iter);
     const bool two_streams = any_self && o->iters > 0 && !(o->flags & CT_ONE_STREAM);
     hipStream_t sst = st;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -489,7 +602,6 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
         CT_CHECK_HIP(hipEventRecord(fork, st));
         CT_CHECK_HIP(hipStreamWaitEvent(sst, fork, 0));
     }
-    int cur = 0;  // which ping-pong self record array is current
     if (any_self) {
         const Schedule sS = schedule_for(d, ref_iter ? M : T, ref_iter ? M : T);
         for (int k = 0; k < o->iters; ++k) {
@@ -502,7 +614,7 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
             cur ^= 1;
         }
     }
-    for (int k = 0; k < o->iters; ++k) {
+    for (int k = 0; k < (fused ? 0 : o->iters); ++k) {
         const bool lagged = !safe_only && (warm || k > 0);
         JobSet A, B;
         A.add(J.f(L.f, L.xrec[0], nullptr));
@@ -593,7 +705,7 @@ static ct_status sinkhorn_grad_impl(const float* x, int64_t T64, const float* y,
         const int nt = (int)L.ntick;
         hipLaunchKernelGGL(k_zero3, dim3((nt + 255) / 256), dim3(256), 0, st, L.tick[0], nt,
                            L.tick[1], nt, L.tick[2], nt);
-        hipLaunchKernelGGL(k_zero3, dim3(1), dim3(256), 0, st, L.counters, 4, nullptr, 0,
+        hipLaunchKernelGGL(k_zero3, dim3(1), dim3(256), 0, st, L.counters, kCounters, nullptr, 0,
                            nullptr, 0);
         CT_CHECK_HIP(hipGetLastError());
     }
@@ -623,7 +735,7 @@ static ct_status sinkhorn_grad_impl(const float* x, int64_t T64, const float* y,
     if (rc) return rc;
 
     hipLaunchKernelGGL(k_grad_x, dim3((T * d + 255) / 256), dim3(256), 0, st, L.dy,
-                       debias ? L.ds : nullptr, T * d, (float)(2.0 / T), grad_x);
+                       debias ? L.ds : nullptr, T * d, (float)(2.0 / T), L.counters + 4, grad_x);
     CT_CHECK_HIP(hipGetLastError());
     if (want_v) {
         ReduceArgs R;
@@ -636,7 +748,7 @@ static ct_status sinkhorn_grad_impl(const float* x, int64_t T64, const float* y,
         CT_CHECK_HIP(hipGetLastError());
         if (grad_w) {
             hipLaunchKernelGGL(k_grad_w, dim3((M + 255) / 256), dim3(256), 0, st, L.gp,
-                               need_ref ? L.qp : nullptr, M, L.bG, L.wsum, grad_w);
+                               need_ref ? L.qp : nullptr, M, L.bG, L.wsum, L.counters + 4, grad_w);
             CT_CHECK_HIP(hipGetLastError());
         }
     } else if (aux) {
@@ -810,7 +922,7 @@ extern "C" ct_status ct_autotune_sinkhorn(int64_t T64, int64_t M64, const ct_sin
     const int n = std::max(pad_keys(T), pad_keys(M));
     hipLaunchKernelGGL(k_zero3, dim3(((int)L.ntick + 255) / 256), dim3(256), 0, st, L.tick[0],
                        (int)L.ntick, L.tick[1], (int)L.ntick, L.tick[2], (int)L.ntick);
-    hipLaunchKernelGGL(k_zero3, dim3(1), dim3(256), 0, st, L.counters, 4, nullptr, 0, nullptr, 0);
+    hipLaunchKernelGGL(k_zero3, dim3(1), dim3(256), 0, st, L.counters, kCounters, nullptr, 0, nullptr, 0);
     hipLaunchKernelGGL(k_synth, dim3((n + 255) / 256), dim3(256), 0, st, T, M, d, pad_keys(T),
                        pad_keys(M), (float)std::sqrt(kappa_d), (float)(-std::log2((double)T)),
                        (float)(-std::log2((double)M)), L.cx, L.cy, L.xrec[0], L.xrec[1], L.xrec[2],
@@ -876,7 +988,7 @@ extern "C" ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* n
     // base (never dereferenced) gives their offset
     char* const probe = reinterpret_cast<char*>(uintptr_t(1) << 20);
     const size_t off = static_cast<size_t>(reinterpret_cast<char*>(sk_layout(probe, 1, 1, 2).counters) - probe);
-    unsigned c[4] = {0u, 0u, 0u, 0u};
+    unsigned c[kCounters] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
     CT_CHECK_HIP(hipMemcpyAsync(c, static_cast<const char*>(ws) + off, sizeof(c),
                                 hipMemcpyDeviceToHost, st));
     CT_CHECK_HIP(hipStreamSynchronize(st));
@@ -886,6 +998,9 @@ extern "C" ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* n
     if (nonfinite) *nonfinite = c[0];
     if (rescued) *rescued = c[1];
     if (resid) *resid = r;
+    if (c[4])
+        return fail(CT_E_DEVICE, "a grid barrier of the last call's fused solve gave up: its "
+                                 "outputs are not valid");
     if (c[0])
         return fail(CT_E_NONFINITE, "the last gradient call saw %u non-finite coordinates or "
                                     "non-positive weights: its outputs are not valid", c[0]);

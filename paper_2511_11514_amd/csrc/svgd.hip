@@ -522,9 +522,41 @@ struct KeyRec {
     static constexpr int N = D == 2 ? 1 : 2;  // float4 records per key
 };
 
+// Mean of the samples (double, fixed order, non-finite coordinates skipped).  The
+// kernel weights depend only on differences x_i - x_j, but the float32 scale by
+// sqrt(log2(e)/h) is not translation invariant: far from the coordinate origin it
+// would round away the low bits of every difference.  Subtracting the mean first
+// (exact for nearby float32 values) keeps them.
+__global__ __launch_bounds__(1024) void k_sv_origin(const float* __restrict__ x, int T, int d,
+                                                    float* __restrict__ out) {
+    __shared__ double red[4][1024];
+    double s[3] = {0.0, 0.0, 0.0}, n = 0.0;
+    for (int i = threadIdx.x; i < T; i += 1024) {
+        const float* p = x + (size_t)i * d;
+        bool ok = true;
+        for (int t = 0; t < d; ++t) ok = ok && isfinite(p[t]);
+        if (!ok) continue;
+        for (int t = 0; t < d; ++t) s[t] += (double)p[t];
+        n += 1.0;
+    }
+    for (int t = 0; t < 3; ++t) red[t][threadIdx.x] = s[t];
+    red[3][threadIdx.x] = n;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int t = 0; t < 4; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) {
+        const double c = red[3][0] > 0.0 ? red[3][0] : 1.0;
+        out[threadIdx.x] = (int)threadIdx.x < d ? (float)(red[threadIdx.x][0] / c) : 0.f;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_svgd_stage(const float* __restrict__ x,
                                                     const float* __restrict__ score, int T, int Tpad,
                                                     int d, float h_fixed, MedState* st,
+                                                    const float* __restrict__ origin,
                                                     float4* __restrict__ qc,
                                                     float4* __restrict__ krec) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -535,7 +567,7 @@ __global__ __launch_bounds__(256) void k_svgd_stage(const float* __restrict__ x,
     if (i < T) {
         float c[3] = {0, 0, 0}, sc[3] = {0, 0, 0};
         for (int t = 0; t < d; ++t) {
-            c[t] = x[(size_t)i * d + t] * s;
+            c[t] = (x[(size_t)i * d + t] - origin[t]) * s;
             sc[t] = score[(size_t)i * d + t];
         }
         qc[i] = make_float4(c[0], c[1], c[2], 0.f);
@@ -696,6 +728,7 @@ struct SvLayout {
     unsigned long long* hist;
     float* score;
     float4* cmed;      // raw coordinates for the median
+    float* origin;     // [4] mean of the samples, subtracted before the bandwidth scale
     float4* qc;
     float4* krec;
     float* part;
@@ -730,6 +763,7 @@ static SvLayout sv_layout(void* ws, int T, int d) {
     L.cand = bracket ? a.take<float>((size_t)cand_cap(T)) : nullptr;
     L.score = a.take<float>((size_t)T * d);
     L.cmed = a.take<float4>(T);
+    L.origin = a.take<float>(4);
     L.qc = a.take<float4>(T);
     L.krec = a.take<float4>((size_t)Tpad * (d == 2 ? 1 : 2));
     L.part = a.take<float>((size_t)2 * d * splits * nqb * 256 * kSvR);
@@ -821,8 +855,10 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
         }
     }
     const int Tpad = pad_keys(T);
+    hipLaunchKernelGGL(k_sv_origin, dim3(1), dim3(1024), 0, st, x, T, d, L.origin);
+    CT_CHECK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_svgd_stage, dim3((Tpad + 255) / 256), dim3(256), 0, st, x, score, T, Tpad,
-                       d, h > 0.f ? h : 0.f, L.st, L.qc, L.krec);
+                       d, h > 0.f ? h : 0.f, L.st, L.origin, L.qc, L.krec);
     CT_CHECK_HIP(hipGetLastError());
     SvgdJob J;
     J.qc = L.qc;

@@ -9,7 +9,7 @@
 
 namespace ct {
 
-template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP>
+template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP, bool EXP = false>
 __global__ __launch_bounds__(kBlock) void k_sweep(Launch L) {
     __shared__ SweepSmem<D, R> sm;
     const int bid = (int)blockIdx.x;
@@ -19,8 +19,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Launch L) {
     const int local = bid - (j ? L.blk_end[j - 1] : 0);
     const int qb = local % J.nqb;
     const int split = local / J.nqb;
-    sweep_unit<D, R, WS, LAGGED, BARY, SEP>(J, qb, split, L.kappa, L.inv_kappa, L.inv_sqrt_kappa,
-                                            sm);
+    sweep_unit<D, R, WS, LAGGED, BARY, SEP, EXP>(J, qb, split, L.kappa, L.inv_kappa,
+                                                 L.inv_sqrt_kappa, sm);
 }
 
 // Merge kernel of the separate-merge mode: blocks of kMergeRows query rows per job
@@ -108,6 +108,7 @@ static hipError_t launch_drws(bool lagged, bool bary, const Launch& L, int nb, h
                               hipEvent_t e0, hipEvent_t e1) {
     if (lagged) {
         if (bary) launch_k(k_sweep<D, R, WS, true, true, SEP>, nb, s, e0, e1, L);
+        else if (L.expanded) launch_k(k_sweep<D, R, WS, true, false, SEP, true>, nb, s, e0, e1, L);
         else launch_k(k_sweep<D, R, WS, true, false, SEP>, nb, s, e0, e1, L);
     } else {
         if (bary) launch_k(k_sweep<D, R, WS, false, true, SEP>, nb, s, e0, e1, L);
@@ -174,7 +175,8 @@ hipError_t launch_sweep(int d, const Schedule& sc, bool lagged, bool bary, const
     if (nblocks <= 0) return hipSuccess;
     double pairs = 0.0;
     for (int j = 0; j < L.njobs; ++j) pairs += (double)L.job[j].nq * L.job[j].nk;
-    const int code = sc.R * 100 + sc.WS * 10 + sc.sep;
+    // code: R, WS and merge kind of the schedule; +1000 for the expanded form
+    const int code = sc.R * 100 + sc.WS * 10 + sc.sep + (lagged && !bary && L.expanded ? 1000 : 0);
     hipEvent_t e0, e1;
     void* tok = profile_kernel_begin(&e0, &e1);
     hipError_t e = d == 2 ? launch_d<2>(sc, lagged, bary, L, nblocks, s, e0, e1)

@@ -83,6 +83,74 @@ __device__ __forceinline__ void pair_lagged(const float4& k, QueryRegs<D, R>& Q)
     }
 }
 
+// Expanded form of the lagged pair, for sweeps without offsets.  Around an origin
+// o shared by a wave (its first query), with q' = x'_i - o and k' = y'_j - o,
+//     e_ij = h_j - |q' - k'|^2 - sh_i = H_j + 2 q'.k' + C_i,
+//     H_j = h_j - |k'|^2 (per key, formed once per wave when the key is staged),
+//     C_i = -|q'|^2 - sh_i (per query),
+// so a pair costs d FMAs, one add, the exp and the accumulate instead of d
+// subtractions, d FMAs, one subtraction, the exp and the accumulate.  The staged
+// key record holds (2k', H_j); the query registers hold q' and C_i.  Near pairs,
+// the only ones whose terms count, have small |q'| and |k'| when the wave's
+// queries lie close together; far pairs round more coarsely, but their terms are
+// negligible.  Rows recomputed with a tracked maximum use the difference form.
+template <int D, int R>
+__device__ __forceinline__ void pair_expanded(const float4& k, QueryRegs<D, R>& Q,
+                                              const float (&C)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        float t;
+        if (D == 2) {
+            t = __builtin_fmaf(Q.q[r][1], k.y, k.z);
+            t = __builtin_fmaf(Q.q[r][0], k.x, t);
+        } else {
+            t = __builtin_fmaf(Q.q[r][2], k.z, k.w);
+            t = __builtin_fmaf(Q.q[r][1], k.y, t);
+            t = __builtin_fmaf(Q.q[r][0], k.x, t);
+        }
+        Q.s[r] += ex2(t + C[r]);
+    }
+}
+
+// Key record (x', y', [z',] h) -> (2k', H) around the origin o (see pair_expanded).
+template <int D>
+__device__ __forceinline__ float4 expand_key(const float4& v, const float (&o)[3]) {
+    const float kx = v.x - o[0], ky = v.y - o[1];
+    if (D == 2) {
+        const float n = __builtin_fmaf(kx, kx, ky * ky);
+        return make_float4(2.f * kx, 2.f * ky, v.z - n, 0.f);
+    }
+    const float kz = v.z - o[2];
+    const float n = __builtin_fmaf(kx, kx, __builtin_fmaf(ky, ky, kz * kz));
+    return make_float4(2.f * kx, 2.f * ky, 2.f * kz, v.w - n);
+}
+
+// Lagged sweep of keys [k0, k1) in the expanded form: the LDS staging of
+// sweep_keys with each key transformed by the lane that loads it.
+template <int D, int R>
+__device__ __forceinline__ void sweep_keys_expanded(const float4* __restrict__ rec, int k0, int k1,
+                                                    const float (&o)[3], const float (&C)[R],
+                                                    QueryRegs<D, R>& Q) {
+    __shared__ float4 kbuf[4][64];
+    const int lane = (int)threadIdx.x & 63;
+    float4* slot = kbuf[__builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6)];
+    if (k0 >= k1) return;
+    float4 nxt = rec[min(k0 + lane, k1 - 1)];
+    for (int k = k0; k < k1; k += 64) {
+        const float4 mine = expand_key<D>(nxt, o);
+        __builtin_amdgcn_wave_barrier();
+        slot[lane] = mine;
+        __builtin_amdgcn_wave_barrier();
+        if (k + 64 < k1) nxt = rec[min(k + 64 + lane, k1 - 1)];
+        const int n = min(64, k1 - k);
+#pragma unroll 2
+        for (int j = 0; j < n; j += 8) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g) pair_expanded<D, R>(slot[j + g], Q, C);
+        }
+    }
+}
+
 // Safe mode over a group of 8 keys.
 template <int D, int R, bool BARY>
 __device__ __forceinline__ void group_safe(const float4 (&k)[8], QueryRegs<D, R>& Q) {
@@ -311,10 +379,11 @@ __device__ __forceinline__ void finish_or_flag(const Job& J, int q, float m, flo
 
 // One work unit: queries of query-block qb, keys of split `split`.
 //   QW = 4 / WS query groups of 64 R queries per block.
-template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP = false>
+template <int D, int R, int WS, bool LAGGED, bool BARY, bool SEP = false, bool EXP = false>
 __device__ __forceinline__ void sweep_unit(const Job& J, int qb, int split, float kappa,
                                            float inv_kappa, float inv_sqrt_kappa,
                                            SweepSmem<D, R>& sm) {
+    static_assert(!EXP || (LAGGED && !BARY), "the expanded form serves lagged sweeps without offsets");
     constexpr int QW = 4 / WS;
     constexpr int NC = 2 + D;                  // components of a partial
     constexpr int QB = QW * 64 * R;            // queries per block
@@ -332,7 +401,35 @@ __device__ __forceinline__ void sweep_unit(const Job& J, int qb, int split, floa
         const int kpw = J.kps / WS;
         const int k0 = min(J.nkpad, s0 + kpart * kpw);
         const int k1 = min(J.nkpad, k0 + kpw);
-        sweep_keys<D, R, LAGGED, BARY>(J.krec, k0, k1, Q);
+        if constexpr (EXP) {
+            // origin: the wave's first query (zero if the wave has none)
+            float o[3] = {0.f, 0.f, 0.f};
+            if (qbase < J.nq) {
+                const float4 c0 = J.qrec[qbase];
+                o[0] = c0.x;
+                o[1] = c0.y;
+                o[2] = D == 3 ? c0.z : 0.f;
+            }
+            float qsave[R][D], C[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                float n = 0.f;
+#pragma unroll
+                for (int t = 0; t < D; ++t) {
+                    qsave[r][t] = Q.q[r][t];
+                    Q.q[r][t] -= o[t];
+                    n = __builtin_fmaf(Q.q[r][t], Q.q[r][t], n);
+                }
+                C[r] = -n - Q.sh[r];
+            }
+            sweep_keys_expanded<D, R>(J.krec, k0, k1, o, C, Q);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int t = 0; t < D; ++t) Q.q[r][t] = qsave[r][t];
+        } else {
+            sweep_keys<D, R, LAGGED, BARY>(J.krec, k0, k1, Q);
+        }
     }
 
     if (threadIdx.x == 0) sm.nflag = 0;

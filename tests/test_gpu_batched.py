@@ -181,3 +181,26 @@ def test_expired_persistent_wait_flags_every_output(ct, monkeypatch):
     for b, (x, y, w) in enumerate(probs):
         r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
         assert rel(gx[b].cpu().numpy(), r.grad_x) < TOL
+
+
+@pytest.mark.parametrize("persistent", MODES)
+def test_problems_far_from_coordinate_origin(ct, persistent):
+    """Each problem shifted far from the coordinate origin, by a different offset:
+    the staging centres every problem on its own mean before the sqrt(kappa)
+    prescale, so the batch matches the oracle at the same bar as near the origin."""
+    probs = []
+    for b, (x, y, w) in enumerate(_ragged(41, 6, 600, 1200)):
+        shift = np.array([300.0 + 170.0 * b, -220.0 + 45.0 * b])
+        probs.append(((x.astype(np.float64) + shift).astype(np.float32),
+                      (y.astype(np.float64) + shift).astype(np.float32), w))
+    eps, iters = 0.01, 25
+    bs = _batch(ct, probs, eps, iters, persistent=persistent)
+    bs.run()
+    torch.cuda.synchronize()
+    gx = bs.split(bs.grad_x.cpu().numpy(), bs.T_off)
+    gw = bs.split(bs.grad_w.cpu().numpy(), bs.M_off)
+    val = bs.value.cpu().numpy()
+    for b, (x, y, w) in enumerate(probs):
+        r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
+        e = (rel(gx[b], r.grad_x), rel(gw[b], r.grad_w), abs(val[b] - r.value) / abs(r.value))
+        assert max(e) < TOL, (b, len(x), len(y), e)

@@ -34,9 +34,12 @@ def _fixture(name):
     return np.load(path, allow_pickle=False)
 
 
+@pytest.mark.parametrize("expanded", [False, True], ids=["difference", "expanded"])
 @pytest.mark.parametrize("name", ["planner_2d_full", "grad_2d_full", "autograd_3d_T4096_M16384",
                                   "roofline_2d_T4096_M16384", "autograd_3d_full"])
-def test_sinkhorn_against_stored_oracle(ct, name):
+def test_sinkhorn_against_stored_oracle(ct, name, expanded):
+    """Each stored workload through the default execution, and through the per-sweep
+    launches with the expanded exponent (CT_EXPANDED)."""
     F = _fixture(name)
     cfg = W.CONFIGS[str(F["workload"])]
     T, M, K = int(F["T"]), int(F["M"]), int(F["iters"])
@@ -44,7 +47,8 @@ def test_sinkhorn_against_stored_oracle(ct, name):
     dev = torch.device("cuda")
     t = lambda a: torch.as_tensor(a, device=dev)
     out = ct.sinkhorn_grad(t(x), t(y), t(w), eps=cfg.eps, iters=K, value=True, grad_w=True,
-                           potentials=True)
+                           potentials=True, expanded=expanded,
+                           fused=False if expanded else None)
     torch.cuda.synchronize()
     pot = out.pot.cpu().numpy()
     f1, g1 = gauge(pot[:T], pot[T:T + M], T, M)
@@ -60,7 +64,7 @@ def test_sinkhorn_against_stored_oracle(ct, name):
         c1, c2 = f1[0] - pot[0], f2[0] - F["f"][0]
         e["f_plus"] = rel(pp[:T] + c1, F["f_plus"] + c2)
         e["g_plus"] = rel(pp[T:T + M] - c1, F["g_plus"] - c2)
-    print(name, " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    print(name, "expanded" if expanded else "", " ".join(f"{k}={v:.2e}" for k, v in e.items()))
     assert max(e.values()) < TOL, e
 
 
@@ -150,7 +154,8 @@ def test_large_workload_svgd_properties(ct):
     assert rel(scd[rows], sref) < TOL
 
 
-def test_large_workload_against_stored_oracle(ct):
+@pytest.mark.parametrize("expanded", [False, True], ids=["difference", "expanded"])
+def test_large_workload_against_stored_oracle(ct, expanded):
     """The large 2-D workload at full size (T = 65536, M = 262144, eps = 0.002,
     K = 500) in the benchmark's launch configuration (autograd form, one stream,
     reference self potential computed once and passed in) against the stored
@@ -166,10 +171,11 @@ def test_large_workload_against_stored_oracle(ct):
     xt, yt, wt = (torch.as_tensor(a, device=dev) for a in (x, y, w))
     q = ct.reference_self_potential(yt, wt, eps=cfg.eps, iters=K)
     xr = xt.clone().requires_grad_(True)
-    S = ct.sinkhorn_divergence(xr, yt, wt, eps=cfg.eps, iters=K, one_stream=True, ref_q=q)
+    S = ct.sinkhorn_divergence(xr, yt, wt, eps=cfg.eps, iters=K, one_stream=True, ref_q=q,
+                               expanded=expanded)
     S.backward()
     out = ct.sinkhorn_grad(xt, yt, wt, eps=cfg.eps, iters=K, value=True, grad_w=True,
-                           potentials=True, one_stream=True, ref_q=q)
+                           potentials=True, one_stream=True, ref_q=q, expanded=expanded)
     torch.cuda.synchronize()
     assert torch.equal(out.grad_x, xr.grad)
     pot = out.pot.cpu().numpy()
@@ -181,7 +187,8 @@ def test_large_workload_against_stored_oracle(ct):
              p=rel(pot[T + M:2 * T + M], F["p"]),
              f_plus=rel(pp[:T].astype(np.float64) + c1, F["f_plus"] + c2),
              p_plus=rel(pp[T + M:2 * T + M], F["p_plus"]))
-    print("roofline_2d_full", " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    print("roofline_2d_full", "expanded" if expanded else "",
+          " ".join(f"{k}={v:.2e}" for k, v in e.items()))
     assert max(e.values()) < TOL, e
     assert np.isfinite(S.item())
 

@@ -93,3 +93,19 @@ def test_bracket_miss_falls_back_to_all_pairs(ct):
     g = W.gmm_params(np.random.default_rng(0), 1, 2, 0.05, 0.1)
     _phi, h, _sc = _gpu(ct, x, g)
     assert h == pytest.approx(0.5 / np.log(T), rel=1e-6)
+
+
+def test_far_from_coordinate_origin(ct):
+    """Samples and mixture shifted far from the coordinate origin: the staging
+    subtracts the samples' mean before the bandwidth scale, so phi matches the
+    oracle at the same bar as near the origin (the bandwidth is a median of
+    differences and does not move)."""
+    x, _y, _w, g = W.config_inputs(W.CONFIGS["grad_2d"], T=1500, M=16)
+    shift = np.array([250.0, -125.0])
+    xs = (x.astype(np.float64) + shift).astype(np.float32)
+    gs = W.GMM(g.weights, (g.means.astype(np.float64) + shift).astype(np.float32), g.sigmas,
+               g.floor)
+    phi, h, sc = _gpu(ct, xs, gs)
+    rphi, rh, rsc = _oracle(xs, gs)
+    e = dict(score=rel(sc, rsc), h=abs(h - rh) / rh, phi=rel(phi, rphi))
+    assert e["score"] < TOL and e["h"] < 1e-6 and e["phi"] < TOL, e
