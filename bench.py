@@ -43,8 +43,12 @@ NOMINAL_RATES = {"add": 128.0, "fma": 64.0, "exp": 32.0}
 N_CU, CLOCK_HZ = 256, 2.4e9
 
 
-def pair_mix(d: int) -> dict:
-    """Instructions per point pair of the lagged sweep."""
+def pair_mix(d: int, expanded: bool = False) -> dict:
+    """Instructions per point pair of the lagged sweep: difference form (d
+    subtractions, d FMAs, one subtraction, the exp, the accumulate) or expanded
+    form (d FMAs, one add, the exp, the accumulate)."""
+    if expanded:
+        return {"add": 2.0, "fma": float(d), "exp": 1.0}
     return {"add": d + 2.0, "fma": float(d), "exp": 1.0}
 
 
@@ -150,14 +154,14 @@ def dominant_sweeps(recs) -> tuple:
     return sum(r[2] for r in sel), sum(r[3] for r in sel), len(sel)
 
 
-def sinkhorn_step(ct, x, y, w, eps, K, gmm=None, ref_q=None, one_stream=False):
+def sinkhorn_step(ct, x, y, w, eps, K, gmm=None, ref_q=None, one_stream=False, expanded=True):
     """One gradient pass: S, dS/dx and dS/dw through the autograd form, then the
     Stein flow on the same samples when a mixture is given."""
     def step():
         xr = x.detach().requires_grad_(True)
         wr = w.detach().requires_grad_(True)
         S = ct.sinkhorn_divergence(xr, y, wr, eps=eps, iters=K, one_stream=one_stream,
-                                   ref_q=ref_q)
+                                   ref_q=ref_q, expanded=expanded)
         S.backward()
         out = [S, xr.grad, wr.grad]
         if gmm is not None:
@@ -208,6 +212,10 @@ def main() -> int:
     ap.add_argument("--grad-2d-only", action="store_true",
                     help="instead of the benchmark line: only the 2-D gradient-field leg "
                          "(T = 4096, M = 16384), for profiling its launches")
+    ap.add_argument("--difference", action="store_true",
+                    help="headline step with the lagged sweeps' exponent in the difference "
+                         "form (CT_DIFFERENCE; default: the expanded form); the roof follows "
+                         "its pair mix")
     ap.add_argument("--stein-only", action="store_true",
                     help="instead of the benchmark line: only the Stein leg (T = 65536), for "
                          "profiling its median and sum kernels")
@@ -281,7 +289,7 @@ def main() -> int:
     ref_ms = e0.elapsed_time(e1)
     print(f"# reference self potential: {ref_ms:.0f} ms", file=sys.stderr, flush=True)
     step = sinkhorn_step(ct, x, y, w, eps, K, gmm=gmm, ref_q=ref_q,
-                         one_stream=not args.two_stream)
+                         one_stream=not args.two_stream, expanded=not args.difference)
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -311,9 +319,10 @@ def main() -> int:
     svgd_pairs = T * T
     total_pairs = sk_pairs + svgd_pairs
     ach = dom_pairs / (dom_ms * 1e-3) / 1e12
-    peak = pair_roof(d, NOMINAL_RATES) / 1e12
+    mix = pair_mix(d, not args.difference)
+    peak = pair_roof(d, NOMINAL_RATES, mix=mix) / 1e12
     probe = ct.probe_alu_rates(str(dev))
-    probe_peak = pair_roof(d, probe, clock=probe["clock_hz"]) / 1e12
+    probe_peak = pair_roof(d, probe, clock=probe["clock_hz"], mix=mix) / 1e12
     traffic = None
     tf = os.path.join(ROOT, "profiles", "sweep_traffic_roofline_2d.json")
     if os.path.exists(tf):
@@ -352,7 +361,8 @@ def main() -> int:
         },
         "roofline": {
             "bound": "alu",
-            "kernel": f"k_sweep (lagged shift, no offsets, d={d})",
+            "kernel": f"k_sweep (lagged shift, no offsets, d={d}"
+                      f"{', difference form' if args.difference else ', expanded exponent'})",
             "achieved": ach,
             "peak": peak,
             "unit": "Tpair/s",
@@ -361,7 +371,7 @@ def main() -> int:
             "launches": n_dom,
             "avg_launch_us": dom_ms / max(n_dom, 1) * 1e3,
             "events": "in the timed steps" if live_events else "one extra step",
-            "pair_mix": pair_mix(d),
+            "pair_mix": mix,
             "nominal_lanes_per_clk_per_cu": NOMINAL_RATES,
             "probe": {k: round(v, 4) for k, v in probe.items()},
             "probe_peak": probe_peak,
@@ -454,7 +464,7 @@ def grad_2d_leg(ct, torch, dev, L, _lib, tuned, steps: int = 20, warmup: int = 3
     dp, dms, nd = dominant_sweeps(read_profile(L, _lib))
     pairs = pairs_per_pass(T, M, K) + T * T
     ach = dp / (dms * 1e-3) / 1e12
-    peak = pair_roof(d, NOMINAL_RATES) / 1e12
+    peak = pair_roof(d, NOMINAL_RATES, mix=pair_mix(d, True)) / 1e12
     traffic = None
     tf = os.path.join(ROOT, "profiles", "sweep_traffic_grad_2d.json")
     if os.path.exists(tf):
@@ -729,7 +739,8 @@ def autograd_3d_leg(ct, torch, dev, reps: int = 2) -> dict:
     assert torch.isfinite(g).all().item()
     ms = e0.elapsed_time(e1) / reps
     pairs = pairs_per_pass(T, M, K)
-    peak = pair_roof(3, NOMINAL_RATES) / 1e12
+    # the expanded pair mix of the lagged sweeps (the stricter roof for the whole pass)
+    peak = pair_roof(3, NOMINAL_RATES, mix=pair_mix(3, True)) / 1e12
     rate = pairs / (ms * 1e-3) / 1e12
     return {"workload": f"autograd_3d: d=3 T={T} M={M} eps={cfg.eps} K={K}, S + dS/dx + dS/dw "
                         "through autograd", "ms_per_pass": ms, "pairs_per_pass": pairs,

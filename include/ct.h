@@ -98,17 +98,24 @@ const char* ct_version(void);
 #define CT_FUSED 256u   /* run all K iterations in one launch of co-resident blocks with a
                            grid-wide barrier after each half-iteration (f and p, then g and q),
                            instead of one launch per sweep; meant for small problems (short
-                           horizons), whose per-iteration launches are bound by launch latency.
-                           Without CT_FUSED or CT_UNFUSED the library picks the fused solve
-                           when one iteration has few enough point pairs. */
-#define CT_UNFUSED 512u /* never use the fused solve (one launch per sweep) */
-#define CT_EXPANDED 1024u /* per-sweep launches: evaluate the lagged sweeps' exponent in the
-                             expanded form around a per-wave origin, h_j - |k'|^2 + 2 q'.k'
-                             - |q'|^2 - shift (d FMAs and one add per pair instead of d
-                             subtractions, d FMAs and one subtraction); the extrapolation pass,
-                             the first (tracked-maximum) sweep and rescued rows keep the
-                             difference form.  Its rounding grows with the spread of the
-                             queries a wave holds. */
+                           horizons), whose per-iteration launches are bound by launch latency */
+#define CT_UNFUSED 512u /* one launch per sweep (neither CT_FUSED nor CT_TINY) */
+#define CT_TINY 2048u   /* run all K iterations in one workgroup with every point and potential
+                           in LDS (no synchronisation beyond the workgroup); CT_E_UNSUPPORTED
+                           when the problem does not fit in the LDS of one workgroup (about
+                           36 bytes per point of x and y).  Without any of CT_FUSED, CT_UNFUSED
+                           and CT_TINY (at most one may be given) the library picks, by the
+                           number of point pairs of one iteration: the one-workgroup solve for
+                           the smallest problems, then the fused solve, then per-sweep
+                           launches. */
+#define CT_DIFFERENCE 1024u /* per-sweep launches: evaluate the lagged sweeps' exponent in the
+                               difference form h_j - |x'_i - y'_j|^2 - shift (d subtractions, d
+                               FMAs, one subtraction per pair).  Default: the expanded form
+                               around an origin shared by a wave, h_j - |k'|^2 + 2 q'.k'
+                               - |q'|^2 - shift with q' = x'_i - o, k' = y'_j - o (d FMAs and
+                               one add per pair).  The extrapolation pass, the first
+                               (tracked-maximum) sweep, rescued rows, the fused, one-workgroup
+                               and batched solves always use the difference form. */
 
 typedef struct ct_sinkhorn_opts {
     int32_t d;      /* 2 or 3 */
@@ -159,7 +166,8 @@ size_t ct_sinkhorn_workspace_size(int64_t T, int64_t M, const ct_sinkhorn_opts* 
  *                               the fused solve gave up (outputs NaN), [7] zero
  * Errors: CT_E_ARG (null x/y/grad_x/ws, eps <= 0 or non-finite, iters < 0, grad_w
  * without CT_GRAD_W, pot missing for CT_WARM_START/CT_REF_CACHED, unknown flag,
- * CT_FUSED together with CT_UNFUSED),
+ * more than one of CT_FUSED, CT_UNFUSED and CT_TINY), CT_E_UNSUPPORTED (CT_TINY for a
+ * problem that does not fit in one workgroup's LDS),
  * CT_E_SHAPE (d not 2/3, T < 1, M < 1, T or M > 2^30), CT_E_WORKSPACE, CT_E_HIP.
  */
 ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const float* w, int64_t M,

@@ -33,7 +33,8 @@ CT_ONE_STREAM = 64
 CT_PERSISTENT = 128
 CT_FUSED = 256
 CT_UNFUSED = 512
-CT_EXPANDED = 1024
+CT_DIFFERENCE = 1024
+CT_TINY = 2048
 
 CT_DYN_DOUBLE_INTEGRATOR = 0
 CT_DYN_UNICYCLE = 1

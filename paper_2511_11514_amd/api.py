@@ -62,8 +62,15 @@ def _opts(d: int, eps: float, iters: int, flags: int) -> L.SinkhornOpts:
     return L.SinkhornOpts(int(d), int(iters), float(eps), int(flags))
 
 
-def _fused_flag(fused: Optional[bool]) -> int:
-    return 0 if fused is None else (L.CT_FUSED if fused else L.CT_UNFUSED)
+def _fused_flag(fused) -> int:
+    """None: the library's size rule; True: CT_FUSED; False: CT_UNFUSED; "tiny": CT_TINY."""
+    if fused is None:
+        return 0
+    if isinstance(fused, str):
+        if fused != "tiny":
+            raise ValueError(f"fused must be None, True, False or 'tiny' (got {fused!r})")
+        return L.CT_TINY
+    return L.CT_FUSED if fused else L.CT_UNFUSED
 
 
 def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = None, *,
@@ -72,15 +79,16 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
                   ref_q: Optional[torch.Tensor] = None, safe: bool = False,
                   potentials: bool = False, aux: bool = False,
                   one_stream: bool = False, static_scratch: bool = False,
-                  fused: Optional[bool] = None, expanded: bool = False) -> SinkhornOut:
+                  fused=None, expanded: bool = True) -> SinkhornOut:
     """Gradient of the (debiased) Sinkhorn divergence; see ct_sinkhorn_grad.
 
     x [T,d], y [M,d], w [M] or None: float32 GPU tensors.
     init: optional [2T+2M] starting potentials (f, g, p, q) -> CT_WARM_START.
     ref_q: optional [M] converged reference self potential -> CT_REF_CACHED.
-    fused: True -> CT_FUSED (all iterations in one launch), False -> CT_UNFUSED,
-    None -> the library's size rule.
-    expanded: CT_EXPANDED (the lagged sweeps' exponent in the expanded form).
+    fused: True -> CT_FUSED (all iterations in one launch), "tiny" -> CT_TINY (all
+    iterations in one workgroup), False -> CT_UNFUSED, None -> the library's size rule.
+    expanded: the lagged sweeps' exponent in the expanded form (default); False ->
+    CT_DIFFERENCE (the difference form).
     static_scratch: call ct_sinkhorn_grad_static (the library's static device
     scratch instead of a workspace; only the outputs are allocated here).
     """
@@ -96,7 +104,7 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
     flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
         (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
         (L.CT_ONE_STREAM if one_stream else 0) | _fused_flag(fused) | \
-        (L.CT_EXPANDED if expanded else 0)
+        (0 if expanded else L.CT_DIFFERENCE)
     pot = None
     if init is not None or ref_q is not None or potentials:
         pot = torch.zeros(2 * T + 2 * M, dtype=torch.float32, device=dev)
@@ -139,7 +147,7 @@ class SinkhornDivergence(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, y, w, eps: float, iters: int, debias: bool = True,
                 one_stream: bool = False, ref_q: Optional[torch.Tensor] = None,
-                expanded: bool = False):
+                expanded: bool = True):
         need_w = bool(w is not None and ctx.needs_input_grad[2])
         out = sinkhorn_grad(x.detach(), y.detach(), None if w is None else w.detach(), eps=eps,
                             iters=iters, debias=debias, value=True, grad_w=need_w,
@@ -159,13 +167,13 @@ class SinkhornDivergence(torch.autograd.Function):
 
 def sinkhorn_divergence(x, y, w=None, *, eps: float, iters: int, debias: bool = True,
                         one_stream: bool = False, ref_q: Optional[torch.Tensor] = None,
-                        expanded: bool = False):
+                        expanded: bool = True):
     """S(x, (y, w)) with autograd (SinkhornDivergence).  ref_q: the reference self
     potential after the same `iters` averaged sweeps (reference_self_potential),
     which does not depend on x: passing it skips those sweeps (CT_REF_CACHED) and
     gives the result of recomputing it up to float32 rounding (the staged
     coordinates are centred on the mean of the points of the call that made q).
-    expanded: CT_EXPANDED (the lagged sweeps' exponent in the expanded form)."""
+    expanded: as for sinkhorn_grad."""
     return SinkhornDivergence.apply(x, y, w, eps, iters, debias, one_stream, ref_q, expanded)
 
 
@@ -428,7 +436,7 @@ def plan(dynamics: str, s0, u, dt: float, Q, R, flow: str, outer: int, step: flo
          y: Optional[torch.Tensor] = None, w: Optional[torch.Tensor] = None,
          gmm: Optional[GMM] = None, grid: Optional[UtilityGrid] = None, eps: float = 0.01,
          iters: int = 100, debias: bool = True, svgd_h: float = 0.0, device=None,
-         fused: Optional[bool] = None):
+         fused=None):
     """Outer planning loop (ct_plan).  flow: "sinkhorn" (y, w), "svgd" (gmm) or
     "svgd_grid" (grid).  fused: as for sinkhorn_grad.  Returns (u [T,m],
     s [T+1,n], hist [outer])."""

@@ -165,6 +165,45 @@ constexpr int kFusedBarWords = (2 * kFusedMaxGroups + 1) * kFusedLine;
 int fused_resident_blocks(int d);
 hipError_t launch_fused(int d, const FusedLaunch& L, int nblocks, hipStream_t s);
 
+// One-workgroup solve of a small problem with everything in LDS (tiny.hip).
+constexpr int kTinyThreads = 1024;                 // 16 waves
+constexpr int kTinyWaves = kTinyThreads / 64;
+constexpr size_t kTinyMaxLds = size_t(64) << 10;   // bytes of LDS the solve may take
+// One soft-min job of a half-iteration, as LDS offsets (in floats).
+struct TinyJob {
+    int rows, keys;        // query rows, key points
+    int qc, kc;            // coordinates of rows / keys (float4 each)
+    int kh;                // key terms h_j = log2 mass_j + kappa * pot_j of the keys
+    int qpot;              // current potential of the rows (shift, averaging)
+    int out_h;             // key terms of the rows, rewritten from the new potential
+    int qlw;               // log2 mass of the rows, or -1: the constant log2a
+    int avg;               // 1: new = (old + T)/2 (self problems; key terms ping-pong)
+    int groups, splits, kps;  // 64-row groups, key ranges, keys per range
+    int task0;             // first task index of the job within its half-iteration
+};
+struct TinyArgs {
+    const float4* cx;      // [T] staged coordinates of x (global)
+    const float4* cy;      // [M] staged coordinates of y
+    const float* log2b;    // [M]
+    float *f, *g, *p, *q;  // [T], [M], [T], [M] starting values in, last iterates out
+    float4* xrec_f;        // [T] records of x: h from f written at the end
+    float4* yrec_g;        // [M] records of y: h from g
+    float4* xrec_p;        // [T] records of x: h from p (the final pass's current array)
+    float4* yrec_q;        // [M] records of y: h from q
+    unsigned* rescued;
+    int T, M, d, iters, lagged0, safe_only, debias, ref_iter;
+    float kappa, inv_kappa, log2a;
+    TinyJob job[2][2];     // [half-iteration][job]
+    int njobs[2], ntasks[2];
+    // LDS offsets (floats)
+    int o_x, o_y, o_lb, o_f, o_g, o_p, o_q, o_hf, o_hg, o_hp, o_hq, o_ps, o_pm;
+    int ntask_max;
+};
+// Plans the tasks and the LDS layout (fills everything but the pointers and the
+// iteration options); false if the layout exceeds kTinyMaxLds.
+bool tiny_plan(int T, int M, int d, bool debias, bool ref_iter, TinyArgs& A, size_t& lds_bytes);
+hipError_t launch_tiny(int d, const TinyArgs& A, size_t lds_bytes, hipStream_t s);
+
 // Per-launch event timing (ct_profile_enable); no-ops when disabled.
 bool profiling();
 void* profile_begin(hipStream_t s);

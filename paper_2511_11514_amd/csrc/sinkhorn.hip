@@ -327,7 +327,7 @@ static SkLayout sk_layout(void* ws, int T, int M, int d) {
 
 static const uint32_t kKnownFlags = CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_WARM_START |
                                     CT_REF_CACHED | CT_SAFE_LSE | CT_ONE_STREAM | CT_FUSED |
-                                    CT_UNFUSED | CT_EXPANDED;
+                                    CT_UNFUSED | CT_DIFFERENCE | CT_TINY;
 
 static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
                           const ct_sinkhorn_opts* o) {
@@ -341,8 +341,11 @@ static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
         return fail(CT_E_ARG, "eps must be finite and > 0");
     if (o->iters < 0) return fail(CT_E_ARG, "iters must be >= 0");
     if (o->flags & ~kKnownFlags) return fail(CT_E_ARG, "unknown flag bits 0x%x", o->flags & ~kKnownFlags);
-    if ((o->flags & CT_FUSED) && (o->flags & CT_UNFUSED))
-        return fail(CT_E_ARG, "CT_FUSED and CT_UNFUSED exclude each other");
+    {
+        const uint32_t ex = o->flags & (CT_FUSED | CT_UNFUSED | CT_TINY);
+        if (ex & (ex - 1))
+            return fail(CT_E_ARG, "CT_FUSED, CT_UNFUSED and CT_TINY exclude each other");
+    }
     if (!x || !y) return fail(CT_E_ARG, "x and y must be non-null");
     return CT_OK;
 }
@@ -350,7 +353,7 @@ static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
 // Launch-time constants of one problem.
 struct SkConsts {
     int d, T, M;
-    int expanded;   // CT_EXPANDED: lagged sweeps without offsets in the expanded form
+    int expanded;   // lagged sweeps without offsets in the expanded form (unless CT_DIFFERENCE)
     float kappa, inv_kappa, inv_sqrt_kappa, log2a;
 };
 
@@ -360,7 +363,7 @@ static SkConsts sk_consts(int T, int M, const ct_sinkhorn_opts* o) {
     c.d = o->d;
     c.T = T;
     c.M = M;
-    c.expanded = (o->flags & CT_EXPANDED) ? 1 : 0;
+    c.expanded = (o->flags & CT_DIFFERENCE) ? 0 : 1;
     c.kappa = (float)kappa_d;
     c.inv_kappa = (float)(1.0 / kappa_d);
     c.inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
@@ -470,11 +473,12 @@ struct ForkJoin {
 // taken when one iteration has at most kFusedAutoPairs point pairs: there the
 // per-sweep launches are bound by launch latency, and two grid barriers per
 // iteration cost less than the four or five kernel boundaries they replace
-// (measured on an MI355X: 1.1-1.4x at 100-500 samples per side; from about 10^6
-// pairs per iteration on, the barriers' cross-die cache write-backs cost more
-// than the launches).  CT_FUSED forces it and CT_UNFUSED rules it out.  The grid
-// has at most kFusedMaxBlocks blocks and never more than can be resident at once.
-constexpr double kFusedAutoPairs = 524288.0;
+// (measured on an MI355X, K = 100, d = 3, T = M: 1.2x at 200-300 samples per side,
+// 1.04x at 500; at 1000, 3*10^6 pairs per iteration, the barriers' cross-die
+// cache write-backs cost more than the launches, 4.3 against 2.7 ms).  CT_FUSED
+// forces it and CT_UNFUSED rules it out.  The grid has at most kFusedMaxBlocks
+// blocks and never more than can be resident at once.
+constexpr double kFusedAutoPairs = 1048576.0;
 constexpr int kFusedMaxBlocks = 512;
 constexpr unsigned kFusedWaitPolls = 1u << 20;
 
@@ -556,6 +560,74 @@ static ct_status run_fused(const SkLayout& L, const SkConsts& c, const SkJobs& J
     return CT_OK;
 }
 
+// One-workgroup solve (all K iterations in one workgroup, everything in LDS; see
+// tiny.hip).  By default it is taken when one iteration has at most
+// kTinyAutoPairs point pairs and the problem fits in the LDS a workgroup may
+// take: one compute unit evaluates such an iteration faster than the GPU can
+// synchronise across its dies (measured on an MI355X, K = 100, d = 3: 0.72 ms at
+// T = M = 100 against 1.24 for the fused solve and 1.39 for per-sweep launches;
+// even with the fused solve at T = M = 200; behind it from 300 on).  CT_TINY
+// forces it (CT_E_UNSUPPORTED when the problem does not fit); CT_FUSED and
+// CT_UNFUSED rule it out.
+constexpr double kTinyAutoPairs = 150000.0;
+
+static size_t device_max_lds() {
+    static std::mutex mu;
+    static std::map<int, size_t> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) v = 0;
+    cache.emplace(dev, (size_t)std::max(0, v));
+    return (size_t)std::max(0, v);
+}
+
+static ct_status run_tiny(const SkLayout& L, const SkConsts& c, const ct_sinkhorn_opts* o,
+                          bool debias, bool ref_iter, bool warm, bool safe_only, hipStream_t st,
+                          bool* ran) {
+    *ran = false;
+    const int T = c.T, M = c.M, d = c.d;
+    const bool forced = o->flags & CT_TINY;
+    const double pairs = 2.0 * T * M + (debias ? (double)T * T : 0.0) +
+                         (ref_iter ? (double)M * M : 0.0);
+    if (!forced && pairs > kTinyAutoPairs) return CT_OK;
+    TinyArgs A;
+    size_t lds = 0;
+    if (!tiny_plan(T, M, d, debias, ref_iter, A, lds) || lds > device_max_lds()) {
+        if (forced)
+            return fail(CT_E_UNSUPPORTED, "T=%d, M=%d needs %zu bytes of LDS; the one-workgroup "
+                                          "solve may take %zu", T, M, lds,
+                        std::min(kTinyMaxLds, device_max_lds()));
+        return CT_OK;
+    }
+    const int cur = o->iters & 1;   // the self record arrays current after K iterations
+    A.cx = L.cx;
+    A.cy = L.cy;
+    A.log2b = L.log2b;
+    A.f = L.f;
+    A.g = L.g;
+    A.p = L.p;
+    A.q = L.q;
+    A.xrec_f = L.xrec[0];
+    A.yrec_g = L.yrec[0];
+    A.xrec_p = L.xrec[2 + cur];
+    A.yrec_q = L.yrec[1 + cur];
+    A.rescued = L.counters + 1;
+    A.d = d;
+    A.iters = o->iters;
+    A.lagged0 = warm ? 1 : 0;
+    A.safe_only = safe_only ? 1 : 0;
+    A.kappa = c.kappa;
+    A.inv_kappa = c.inv_kappa;
+    A.log2a = c.log2a;
+    CT_CHECK_HIP(launch_tiny(d, A, lds, st));
+    *ran = true;
+    return CT_OK;
+}
+
 // Iterate-and-extrapolate for one problem whose arrays are staged in L.
 static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_opts* o,
                              hipStream_t st, const ForkJoin* fj) {
@@ -574,8 +646,14 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     int cur = 0;  // which ping-pong self record array is current
     bool fused = false;
     if (o->iters > 0 && !(o->flags & CT_UNFUSED)) {
-        ct_status rc = run_fused(L, c, J, o, debias, ref_iter, warm, safe_only, st, &fused);
-        if (rc) return rc;
+        if (!(o->flags & CT_FUSED)) {
+            ct_status rc = run_tiny(L, c, o, debias, ref_iter, warm, safe_only, st, &fused);
+            if (rc) return rc;
+        }
+        if (!fused && !(o->flags & CT_TINY)) {
+            ct_status rc = run_fused(L, c, J, o, debias, ref_iter, warm, safe_only, st, &fused);
+            if (rc) return rc;
+        }
         if (fused) cur = o->iters & 1;
     }
 

@@ -38,8 +38,9 @@ def _fixture(name):
 @pytest.mark.parametrize("name", ["planner_2d_full", "grad_2d_full", "autograd_3d_T4096_M16384",
                                   "roofline_2d_T4096_M16384", "autograd_3d_full"])
 def test_sinkhorn_against_stored_oracle(ct, name, expanded):
-    """Each stored workload through the default execution, and through the per-sweep
-    launches with the expanded exponent (CT_EXPANDED)."""
+    """Each stored workload through the default execution (whose per-sweep launches
+    use the expanded exponent), and through the per-sweep launches with the
+    difference form (CT_DIFFERENCE)."""
     F = _fixture(name)
     cfg = W.CONFIGS[str(F["workload"])]
     T, M, K = int(F["T"]), int(F["M"]), int(F["iters"])
@@ -48,7 +49,7 @@ def test_sinkhorn_against_stored_oracle(ct, name, expanded):
     t = lambda a: torch.as_tensor(a, device=dev)
     out = ct.sinkhorn_grad(t(x), t(y), t(w), eps=cfg.eps, iters=K, value=True, grad_w=True,
                            potentials=True, expanded=expanded,
-                           fused=False if expanded else None)
+                           fused=None if expanded else False)
     torch.cuda.synchronize()
     pot = out.pot.cpu().numpy()
     f1, g1 = gauge(pot[:T], pot[T:T + M], T, M)

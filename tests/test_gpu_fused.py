@@ -158,3 +158,95 @@ def test_fused_barrier_give_up_is_flagged(ct, monkeypatch):
     monkeypatch.delenv("CT_FUSED_WAIT_POLLS")
     assert call() == L.CT_OK
     assert torch.isfinite(gx).all() and torch.isfinite(gw).all() and torch.isfinite(val).all()
+
+
+# ---------------------------------------------------------------- one workgroup (CT_TINY)
+
+@pytest.mark.parametrize("d,T,M,eps,iters", [
+    (2, 1, 1, 0.01, 5),
+    (2, 37, 53, 0.01, 30),
+    (3, 100, 100, 0.01, 100),
+    (2, 256, 512, 0.01, 100),
+    (3, 300, 300, 0.01, 50),
+    (2, 65, 1100, 0.005, 40),
+    (3, 700, 600, 0.02, 20),
+])
+def test_one_workgroup_matches_oracle(ct, d, T, M, eps, iters):
+    cfg = W.CONFIGS["grad_2d"] if d == 2 else W.CONFIGS["autograd_3d"]
+    x, y, w, _g = W.config_inputs(cfg, T=T, M=M)
+    print(f"one-workgroup parity d={d} T={T} M={M} eps={eps} K={iters}", flush=True)
+    g = _run(ct, x, y, w, eps, iters, fused="tiny")
+    r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
+    e = _errs(g, r, T, M, w)
+    print(" ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    assert max(e.values()) < TOL, e
+
+
+def test_one_workgroup_agrees_with_other_executions_and_is_deterministic(ct):
+    x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=300, M=700)
+    w = W.positive_weights(np.random.default_rng(5), 700)
+    a = _run(ct, x, y, w, 0.01, 60, fused="tiny")
+    b = _run(ct, x, y, w, 0.01, 60, fused=False)
+    c = _run(ct, x, y, w, 0.01, 60, fused="tiny")
+    for k in ("grad_x", "grad_w"):
+        assert rel(a[k], b[k]) < 2e-6, (k, rel(a[k], b[k]))
+    for k in ("grad_x", "grad_w", "value", "pot"):
+        assert np.array_equal(a[k], c[k]), k
+
+
+def test_one_workgroup_not_debiased_warm_start_rescue_and_safe_mode(ct):
+    x, y, _w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=200, M=450)
+    T, M = 200, 450
+    w = W.positive_weights(np.random.default_rng(13), M)
+    g = _run(ct, x, y, w, 0.01, 40, fused="tiny", debias=False)
+    r = oracle.sinkhorn(x, y, w, eps=0.01, iters=40, debias=False)
+    e = _errs(g, r, T, M, w, debias=False)
+    assert max(e.values()) < TOL, ("not debiased", e)
+    # a warm start far from the fixed point: every row's lagged shift is unusable in
+    # the first iteration and the rows are recomputed with a tracked maximum
+    init = np.zeros(2 * T + 2 * M, dtype=np.float64)
+    init[:T] = 3.0
+    init[T:T + M] = -1.0
+    init[T + M:2 * T + M] = -2.0
+    g = _run(ct, x, y, w, 0.01, 20, fused="tiny", init=init)
+    assert g["aux"][4] > 0, "rescue path was not exercised"
+    r = oracle.sinkhorn(x, y, w, eps=0.01, iters=20,
+                        init=(init[:T], init[T:T + M], init[T + M:2 * T + M], init[2 * T + M:]))
+    e = _errs(g, r, T, M, w)
+    assert max(e.values()) < TOL, ("rescue", e)
+    g = _run(ct, x, y, w, 0.01, 30, fused="tiny", safe=True)
+    r = oracle.sinkhorn(x, y, w, eps=0.01, iters=30)
+    e = _errs(g, r, T, M, w)
+    assert max(e.values()) < TOL, ("safe", e)
+
+
+def test_one_workgroup_cached_reference_and_planner(ct):
+    cfg = W.CONFIGS["planner_2d"]
+    x, y, w, _g = W.config_inputs(cfg)
+    dev = torch.device("cuda")
+    q = ct.reference_self_potential(torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev),
+                                    eps=cfg.eps, iters=cfg.iters)
+    g = _run(ct, x, y, w, cfg.eps, cfg.iters, fused="tiny", ref_q=q.cpu().numpy())
+    full = _run(ct, x, y, w, cfg.eps, cfg.iters, fused=False)
+    assert rel(g["grad_x"], full["grad_x"]) < TOL
+    assert rel(g["grad_w"], full["grad_w"]) < TOL
+    # one planner step through the one-workgroup solve against the oracle planner
+    e = cfg.extra
+    u0 = np.random.default_rng(cfg.seed + 1).normal(size=(cfg.T, 2)) * e["u_std"]
+    s0 = np.array(e["s0"])
+    Q, R = np.eye(2), 0.01 * np.eye(2)
+    u1, _s, hist = ct.plan("double_integrator", s0, u0, e["dt"], Q, R, "sinkhorn", 1, 0.5,
+                           y=torch.as_tensor(y, device=dev), w=torch.as_tensor(w, device=dev),
+                           eps=cfg.eps, iters=cfg.iters, fused="tiny")
+    r_u1, _rs, r_obj, _ra, _rv = oracle.plan_step("double_integrator", s0, u0, e["dt"], Q, R,
+                                                 "sinkhorn", step=0.5, y=y, w=w, eps=cfg.eps,
+                                                 iters=cfg.iters)
+    assert abs(hist[0] - r_obj) / abs(r_obj) < TOL
+    assert rel(u1 - u0, r_u1 - u0) < TOL
+
+
+def test_one_workgroup_rejects_problems_beyond_its_lds(ct):
+    x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=1000, M=3000)
+    with pytest.raises(ct.CtError) as e:
+        _run(ct, x, y, w, 0.01, 5, fused="tiny")
+    assert e.value.code == -6

@@ -312,18 +312,18 @@ def test_repeated_calls_are_bitwise_identical(ct, d, T, M):
     (3, 777, 2049, 0.02, 30),
     (2, 4096, 16384, 0.002, 60),
 ])
-def test_expanded_form_matches_oracle(ct, d, T, M, eps, iters):
-    """CT_EXPANDED (the lagged sweeps' exponent in the expanded form around a
-    per-wave origin) against the oracle at the same bar as the difference form."""
+def test_difference_form_matches_oracle(ct, d, T, M, eps, iters):
+    """CT_DIFFERENCE (the lagged sweeps' exponent in the difference form; the
+    default is the expanded form around a per-wave origin) against the oracle."""
     cfg = W.CONFIGS["grad_2d"] if d == 2 else W.CONFIGS["autograd_3d"]
     x, y, w, _g = W.config_inputs(cfg, T=T, M=M)
     dev = torch.device("cuda")
     t = lambda a: torch.as_tensor(a, device=dev)
     out = ct.sinkhorn_grad(t(x), t(y), t(w), eps=eps, iters=iters, value=True, grad_w=True,
-                           potentials=True, aux=True, expanded=True, fused=False)
+                           potentials=True, aux=True, expanded=False, fused=False)
     torch.cuda.synchronize()
     g = {k: (None if v is None else v.cpu().numpy()) for k, v in out.__dict__.items()}
     r = _oracle(x, y, w, eps, iters)
     errs = _compare(g, r, T, M, w)
-    print(f"expanded d={d} T={T} M={M} eps={eps} K={iters}: " +
+    print(f"difference form d={d} T={T} M={M} eps={eps} K={iters}: " +
           " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
