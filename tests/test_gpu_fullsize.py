@@ -27,6 +27,17 @@ GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 TOL = 1e-5
 
 
+TABLE = os.path.join(os.path.dirname(GOLD), "..", "paper_2511_11514_amd", "tuning", "mi355x.txt")
+
+
+@pytest.fixture
+def stored_schedules(ct):
+    """The stored MI355X schedule table (what the benchmark loads), for one test."""
+    ct.tuning_load(os.path.normpath(TABLE))
+    yield
+    ct.tuning_clear()
+
+
 def _fixture(name):
     path = os.path.join(GOLD, name + ".npz")
     if not os.path.exists(path):
@@ -156,10 +167,11 @@ def test_large_workload_svgd_properties(ct):
 
 
 @pytest.mark.parametrize("expanded", [False, True], ids=["difference", "expanded"])
-def test_large_workload_against_stored_oracle(ct, expanded):
+def test_large_workload_against_stored_oracle(ct, stored_schedules, expanded):
     """The large 2-D workload at full size (T = 65536, M = 262144, eps = 0.002,
-    K = 500) in the benchmark's launch configuration (autograd form, one stream,
-    reference self potential computed once and passed in) against the stored
+    K = 500) in the benchmark's launch configuration (stored schedule table,
+    autograd form, one stream, reference self potential computed once and passed
+    in) against the stored
     FP64 oracle pass of the cross and trajectory-self solves: the gradient with
     respect to the samples, the gauge-fixed cross potentials, the self potential
     and the extrapolated ones."""
