@@ -113,9 +113,10 @@ const char* ct_version(void);
                                FMAs, one subtraction per pair).  Default: the expanded form
                                around an origin shared by a wave, h_j - |k'|^2 + 2 q'.k'
                                - |q'|^2 - shift with q' = x'_i - o, k' = y'_j - o (d FMAs and
-                               one add per pair).  The extrapolation pass, the first
-                               (tracked-maximum) sweep, rescued rows, the fused, one-workgroup
-                               and batched solves always use the difference form. */
+                               one add per pair); likewise the batched lockstep launches.  The
+                               extrapolation pass, the first (tracked-maximum) sweep, rescued
+                               rows, the fused and one-workgroup solves and the batched
+                               persistent kernel always use the difference form. */
 
 typedef struct ct_sinkhorn_opts {
     int32_t d;      /* 2 or 3 */
@@ -237,7 +238,8 @@ ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* nonfinite, u
  *                             (every problem needs T_b >= 1, M_b >= 1)
  *   x, y, w, grad_x, grad_w   concatenations in that order (w may be NULL)
  *   value         device [B] or NULL (requires CT_VALUE)
- * Flags: CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_SAFE_LSE, CT_PERSISTENT (others: CT_E_ARG).
+ * Flags: CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_SAFE_LSE, CT_PERSISTENT, CT_DIFFERENCE (others:
+ * CT_E_ARG).
  * The workspace must first be prepared for this batch (same B, offsets, d, iters,
  * flags) by ct_sinkhorn_batched_prepare, which builds the work list on the host
  * and copies it into `ws`; ct_sinkhorn_grad_batched itself only enqueues kernels

@@ -198,9 +198,11 @@ class BatchedOut:
 def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor],
                           ws: Optional[Sequence[torch.Tensor]] = None, *, eps: float, iters: int,
                           debias: bool = True, value: bool = False, grad_w: bool = False,
-                          safe: bool = False, persistent: bool = False) -> BatchedOut:
+                          safe: bool = False, persistent: bool = False,
+                          expanded: bool = True) -> BatchedOut:
     """Many independent problems (ragged T_b, M_b): lockstep launches over all of
-    them (default) or one persistent launch (persistent=True)."""
+    them (default) or one persistent launch (persistent=True).  expanded: as for
+    sinkhorn_grad (the lockstep launches' lagged sweeps)."""
     B = len(xs)
     if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
         raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
@@ -216,7 +218,7 @@ def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor]
     w = None if ws is None else _req(torch.cat([_req(t, "w", dev) for t in ws]), "w")
     flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
         (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
-        (L.CT_PERSISTENT if persistent else 0)
+        (L.CT_PERSISTENT if persistent else 0) | (0 if expanded else L.CT_DIFFERENCE)
     o = _opts(d, eps, iters, flags)
     to = T_off.ctypes.data_as(L.PI64)
     mo = M_off.ctypes.data_as(L.PI64)
@@ -242,7 +244,7 @@ class BatchedSinkhorn:
 
     def __init__(self, xs, ys, ws=None, *, eps: float, iters: int, debias: bool = True,
                  value: bool = False, grad_w: bool = False, safe: bool = False,
-                 persistent: bool = False):
+                 persistent: bool = False, expanded: bool = True):
         B = len(xs)
         if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
             raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
@@ -259,7 +261,7 @@ class BatchedSinkhorn:
         self.w = None if ws is None else _req(torch.cat([_req(t, "w", self.dev) for t in ws]), "w")
         flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
             (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
-            (L.CT_PERSISTENT if persistent else 0)
+            (L.CT_PERSISTENT if persistent else 0) | (0 if expanded else L.CT_DIFFERENCE)
         self.o = _opts(self.d, eps, iters, flags)
         self._to = self.T_off.ctypes.data_as(L.PI64)
         self._mo = self.M_off.ctypes.data_as(L.PI64)

@@ -560,7 +560,8 @@ ct_status b_validate(int B, const int64_t* To, const int64_t* Mo, const ct_sinkh
     if (o->d != 2 && o->d != 3) return fail(CT_E_SHAPE, "d must be 2 or 3");
     if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(CT_E_ARG, "eps must be finite and > 0");
     if (o->iters < 0) return fail(CT_E_ARG, "iters must be >= 0");
-    if (o->flags & ~(uint32_t)(CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_SAFE_LSE | CT_PERSISTENT))
+    if (o->flags & ~(uint32_t)(CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_SAFE_LSE | CT_PERSISTENT |
+                               CT_DIFFERENCE))
         return fail(CT_E_ARG, "unsupported flags for the batched path");
     if (To[0] != 0 || Mo[0] != 0) return fail(CT_E_SHAPE, "offsets must start at 0");
     S = BatchSizes{0, 0, 0, 0};
@@ -880,6 +881,7 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
         T0.kappa = (float)kappa_d;
         T0.inv_kappa = (float)(1.0 / kappa_d);
         T0.inv_sqrt_kappa = (float)(1.0 / std::sqrt(kappa_d));
+        T0.expanded = (o->flags & CT_DIFFERENCE) ? 0 : 1;
         const Schedule lsc = info.sc;
         auto run_kind = [&](int k, bool lagged, bool bary) -> ct_status {
             if (info.njobs[k] == 0) return CT_OK;

@@ -116,6 +116,7 @@ struct TabLaunch {
     const int* mrg_end;
     int njobs;
     int nblocks, nmerge;
+    int expanded;          // 1: lagged sweeps without offsets use the expanded pair form
     float kappa, inv_kappa, inv_sqrt_kappa;
 };
 // Plan nqb/splits/kps of `j` so that one block sweeps about `pairs_per_block` pairs.

@@ -22,7 +22,7 @@ __device__ __forceinline__ int owner(const int* end, int n, int b) {
     return lo;
 }
 
-template <int D, int R, int WS, bool LAGGED, bool BARY>
+template <int D, int R, int WS, bool LAGGED, bool BARY, bool EXP = false>
 __global__ __launch_bounds__(kBlock) void k_sweep_tab(TabLaunch L) {
     __shared__ SweepSmem<D, R> sm;
     const int bid = (int)blockIdx.x;
@@ -31,8 +31,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep_tab(TabLaunch L) {
     const int local = bid - (j ? L.blk_end[j - 1] : 0);
     const int qb = local % J.nqb;
     const int split = local / J.nqb;
-    sweep_unit<D, R, WS, LAGGED, BARY, true>(J, qb, split, L.kappa, L.inv_kappa, L.inv_sqrt_kappa,
-                                             sm);
+    sweep_unit<D, R, WS, LAGGED, BARY, true, EXP>(J, qb, split, L.kappa, L.inv_kappa,
+                                                  L.inv_sqrt_kappa, sm);
 }
 
 template <int D, bool LAGGED, bool BARY>
@@ -66,6 +66,7 @@ static hipError_t tab_drw(bool lagged, bool bary, const TabLaunch& L, hipStream_
     const dim3 g(L.nblocks), b(kBlock);
     if (lagged) {
         if (bary) hipLaunchKernelGGL((k_sweep_tab<D, R, WS, true, true>), g, b, 0, s, L);
+        else if (L.expanded) hipLaunchKernelGGL((k_sweep_tab<D, R, WS, true, false, true>), g, b, 0, s, L);
         else hipLaunchKernelGGL((k_sweep_tab<D, R, WS, true, false>), g, b, 0, s, L);
     } else {
         if (bary) hipLaunchKernelGGL((k_sweep_tab<D, R, WS, false, true>), g, b, 0, s, L);

@@ -204,3 +204,19 @@ def test_problems_far_from_coordinate_origin(ct, persistent):
         r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
         e = (rel(gx[b], r.grad_x), rel(gw[b], r.grad_w), abs(val[b] - r.value) / abs(r.value))
         assert max(e) < TOL, (b, len(x), len(y), e)
+
+
+def test_lockstep_difference_form_matches_oracle(ct):
+    """The lockstep launches with the difference form (CT_DIFFERENCE; the default
+    lagged sweeps use the expanded exponent) against the oracle."""
+    probs = _ragged(29, 7, 900, 1600)
+    eps, iters = 0.01, 25
+    bs = _batch(ct, probs, eps, iters, expanded=False)
+    bs.run()
+    torch.cuda.synchronize()
+    gx = bs.split(bs.grad_x.cpu().numpy(), bs.T_off)
+    gw = bs.split(bs.grad_w.cpu().numpy(), bs.M_off)
+    for b, (x, y, w) in enumerate(probs):
+        r = oracle.sinkhorn(x, y, w, eps=eps, iters=iters)
+        e = (rel(gx[b], r.grad_x), rel(gw[b], r.grad_w))
+        assert max(e) < TOL, (b, len(x), len(y), e)
