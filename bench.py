@@ -136,6 +136,112 @@ def cpu_baseline(x, y, w, eps, iters_sample: int, one_core_rows: int = 2048) -> 
     return res
 
 
+_ONE_CORE_CFG = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import oracle
+import workloads as W
+cfg = W.CONFIGS[{name!r}]
+x, y, w, _g = W.config_inputs(cfg, T={T}, M={M})
+x = x[:{rows}]
+logb = np.log(w.astype(np.float64) / np.sum(w, dtype=np.float64))
+oracle.lse_update(x[:16], y, logb, np.zeros(len(y)), cfg.eps)
+best = float("inf")
+for _ in range(3):
+    t0 = time.perf_counter()
+    oracle.lse_update(x, y, logb, np.zeros(len(y)), cfg.eps)
+    best = min(best, time.perf_counter() - t0)
+print(json.dumps({{"pairs": float(len(x)) * len(y), "s": best}}))
+"""
+
+
+def oracle_configs(ct, torch, dev) -> None:
+    """The FP64 oracle, as it stands, timed per workload on the host cores beside
+    the GPU path on the same workload: one JSON line per workload with the
+    oracle's rate on every host thread (a bounded sample: the whole pass where it
+    takes seconds, else a few iterations of the same solves plus the final pass,
+    scaled by pair counts), its rate on one core (a child process with one thread:
+    one soft-min update of up to 2048 rows against all keys, best of three) and
+    the GPU's time for one full pass (S, dS/dx and dS/dw; the batch: its
+    gradients), best of three after a warm-up."""
+    import subprocess
+    import numpy as np
+    import oracle
+    import workloads as W
+    threads = omp_threads()
+    z = np.zeros(16)
+    oracle.lse_update(np.zeros((16, 2)), np.zeros((16, 2)), z, z, 0.01)   # load the C library
+
+    def gpu_best(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        return best
+
+    def one_core(name, T=None, M=None, rows=2048):
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        code = _ONE_CORE_CFG.format(root=ROOT, name=name, T=T, M=M, rows=rows)
+        r = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE,
+                           text=True, check=True)
+        one = json.loads(r.stdout.strip().splitlines()[-1])
+        return one["pairs"] / one["s"]
+
+    for name, sample_iters in (("planner_2d", None), ("grad_2d", 10), ("autograd_3d", 2),
+                               ("roofline_2d", 1)):
+        cfg = W.CONFIGS[name]
+        x, y, w, _g = W.config_inputs(cfg)
+        T, M, K = len(x), len(y), cfg.iters
+        it = K if sample_iters is None else sample_iters
+        full = pairs_per_pass(T, M, K)
+        t0 = time.perf_counter()
+        oracle.sinkhorn(x, y, w, eps=cfg.eps, iters=it)
+        dt = time.perf_counter() - t0
+        sample = pairs_per_pass(T, M, it)
+        rate = sample / dt
+        xt, yt, wt = (torch.as_tensor(a, device=dev) for a in (x, y, w))
+        g = gpu_best(lambda: ct.sinkhorn_grad(xt, yt, wt, eps=cfg.eps, iters=K, value=True,
+                                              grad_w=True), reps=1 if name == "roofline_2d" else 3)
+        row = {"workload": name, "d": cfg.d, "T": T, "M": M, "K": K, "pairs_per_pass": full,
+               "oracle_sample": f"{it} iterations + final pass ({sample:.3e} pairs) in {dt:.2f} s",
+               "oracle_pairs_per_s": rate, "oracle_threads": threads,
+               "oracle_s_per_pass": full / rate,
+               "oracle_one_core_pairs_per_s": one_core(name), "gpu_s_per_pass": g,
+               "gpu_over_oracle": (full / rate) / g}
+        print(json.dumps(row), flush=True)
+    # the ragged batch: 16 of its problems through the oracle (5 iterations each, scaled to
+    # the batch's pair count), against the batched GPU path on the whole batch
+    cfg = W.CONFIGS["batched_2d"]
+    probs = W.batch_inputs(cfg)
+    full = sum(pairs_per_pass(len(p[0]), len(p[1]), cfg.iters, ref=False, value=False)
+               for p in probs)
+    pick = list(range(0, len(probs), 16))
+    t0 = time.perf_counter()
+    sample = 0.0
+    for b in pick:
+        xb, yb, wb = probs[b]
+        oracle.sinkhorn(xb, yb, wb, eps=cfg.eps, iters=5, want_value=False, want_grad_w=False)
+        sample += pairs_per_pass(len(xb), len(yb), 5, ref=False, value=False)
+    dt = time.perf_counter() - t0
+    rate = sample / dt
+    xs = [torch.as_tensor(p[0], device=dev) for p in probs]
+    ys = [torch.as_tensor(p[1], device=dev) for p in probs]
+    bs = ct.BatchedSinkhorn(xs, ys, None, eps=cfg.eps, iters=cfg.iters)
+    g = gpu_best(bs.run)
+    print(json.dumps({"workload": "batched_2d", "problems": len(probs), "K": cfg.iters,
+                      "pairs_per_batch": full,
+                      "oracle_sample": f"{len(pick)} problems x 5 iterations + final pass "
+                                       f"({sample:.3e} pairs) in {dt:.2f} s",
+                      "oracle_pairs_per_s": rate, "oracle_threads": threads,
+                      "oracle_s_per_batch": full / rate, "gpu_s_per_batch": g,
+                      "gpu_over_oracle": (full / rate) / g}), flush=True)
+
+
 def read_profile(L, _lib) -> list:
     """Launch records of ct_profile_*: (kind0, kind1, pairs, ms) per launch."""
     kind = (ctypes.c_int32 * 4)()
@@ -216,6 +322,9 @@ def main() -> int:
                     help="headline step with the lagged sweeps' exponent in the difference "
                          "form (CT_DIFFERENCE; default: the expanded form); the roof follows "
                          "its pair mix")
+    ap.add_argument("--oracle-configs", action="store_true",
+                    help="instead of the benchmark line: the FP64 oracle timed per workload on "
+                         "the host cores (all threads and one core) beside the GPU's full pass")
     ap.add_argument("--stein-only", action="store_true",
                     help="instead of the benchmark line: only the Stein leg (T = 65536), for "
                          "profiling its median and sum kernels")
@@ -241,6 +350,10 @@ def main() -> int:
         return 0
     if args.grid:
         grid_leg(ct, torch, dev)
+        return 0
+    if args.oracle_configs:
+        ct.tuning_load(os.path.join(ROOT, "paper_2511_11514_amd", "tuning", "mi355x.txt"))
+        oracle_configs(ct, torch, dev)
         return 0
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
