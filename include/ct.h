@@ -99,15 +99,23 @@ const char* ct_version(void);
                            grid-wide barrier after each half-iteration (f and p, then g and q),
                            instead of one launch per sweep; meant for small problems (short
                            horizons), whose per-iteration launches are bound by launch latency */
-#define CT_UNFUSED 512u /* one launch per sweep (neither CT_FUSED nor CT_TINY) */
+#define CT_UNFUSED 512u /* one launch per sweep (none of CT_FUSED, CT_TINY, CT_MESH) */
 #define CT_TINY 2048u   /* run all K iterations in one workgroup with every point and potential
                            in LDS (no synchronisation beyond the workgroup); CT_E_UNSUPPORTED
                            when the problem does not fit in the LDS of one workgroup (about
-                           36 bytes per point of x and y).  Without any of CT_FUSED, CT_UNFUSED
-                           and CT_TINY (at most one may be given) the library picks, by the
-                           number of point pairs of one iteration: the one-workgroup solve for
-                           the smallest problems, then the fused solve, then per-sweep
-                           launches. */
+                           48 to 80 bytes per point of x and y, depending on the self terms). */
+#define CT_MESH 4096u   /* run all K iterations in one launch of 2 to 64 workgroups, each with
+                           every point in LDS and at most 64 rows of x and of y of its own;
+                           the workgroups exchange their rows' new potentials through
+                           versioned words in device memory (relaxed device-scope atomics),
+                           with no grid barrier; CT_E_UNSUPPORTED when it cannot plan (T and
+                           M both at most 64, more than 4096 of either, or the points do not
+                           fit in one workgroup's LDS).  Without any of CT_FUSED,
+                           CT_UNFUSED, CT_TINY and CT_MESH (at most one may be given) the
+                           library picks, by the point pairs of one iteration: the
+                           one-workgroup solve up to 4e4, the exchange solve up to 2e7 where
+                           it plans, else the one-workgroup solve up to 1.5e5, the fused
+                           solve up to 1.05e6, and per-sweep launches beyond. */
 #define CT_DIFFERENCE 1024u /* per-sweep launches: evaluate the lagged sweeps' exponent in the
                                difference form h_j - |x'_i - y'_j|^2 - shift (d subtractions, d
                                FMAs, one subtraction per pair).  Default: the expanded form
@@ -164,11 +172,13 @@ size_t ct_sinkhorn_workspace_size(int64_t T, int64_t M, const ct_sinkhorn_opts* 
  *                               shift was unusable and that were recomputed with a
  *                               tracked maximum, [5] number of non-finite inputs or
  *                               non-positive weights, [6] 1 if a grid barrier of
- *                               the fused solve gave up (outputs NaN), [7] zero
+ *                               the fused solve or a wait of the exchange solve
+ *                               gave up (outputs NaN), [7] zero
  * Errors: CT_E_ARG (null x/y/grad_x/ws, eps <= 0 or non-finite, iters < 0, grad_w
  * without CT_GRAD_W, pot missing for CT_WARM_START/CT_REF_CACHED, unknown flag,
- * more than one of CT_FUSED, CT_UNFUSED and CT_TINY), CT_E_UNSUPPORTED (CT_TINY for a
- * problem that does not fit in one workgroup's LDS),
+ * more than one of CT_FUSED, CT_UNFUSED, CT_TINY and CT_MESH), CT_E_UNSUPPORTED
+ * (CT_TINY for a problem that does not fit in one workgroup's LDS, CT_MESH for one it
+ * cannot plan),
  * CT_E_SHAPE (d not 2/3, T < 1, M < 1, T or M > 2^30), CT_E_WORKSPACE, CT_E_HIP.
  */
 ct_status ct_sinkhorn_grad(const float* x, int64_t T, const float* y, const float* w, int64_t M,

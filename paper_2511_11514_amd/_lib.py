@@ -35,6 +35,7 @@ CT_FUSED = 256
 CT_UNFUSED = 512
 CT_DIFFERENCE = 1024
 CT_TINY = 2048
+CT_MESH = 4096
 
 CT_DYN_DOUBLE_INTEGRATOR = 0
 CT_DYN_UNICYCLE = 1

@@ -63,13 +63,14 @@ def _opts(d: int, eps: float, iters: int, flags: int) -> L.SinkhornOpts:
 
 
 def _fused_flag(fused) -> int:
-    """None: the library's size rule; True: CT_FUSED; False: CT_UNFUSED; "tiny": CT_TINY."""
+    """None: the library's size rule; True: CT_FUSED; False: CT_UNFUSED; "tiny": CT_TINY;
+    "mesh": CT_MESH."""
     if fused is None:
         return 0
     if isinstance(fused, str):
-        if fused != "tiny":
-            raise ValueError(f"fused must be None, True, False or 'tiny' (got {fused!r})")
-        return L.CT_TINY
+        if fused not in ("tiny", "mesh"):
+            raise ValueError(f"fused must be None, True, False, 'tiny' or 'mesh' (got {fused!r})")
+        return L.CT_TINY if fused == "tiny" else L.CT_MESH
     return L.CT_FUSED if fused else L.CT_UNFUSED
 
 
@@ -86,7 +87,9 @@ def sinkhorn_grad(x: torch.Tensor, y: torch.Tensor, w: Optional[torch.Tensor] = 
     init: optional [2T+2M] starting potentials (f, g, p, q) -> CT_WARM_START.
     ref_q: optional [M] converged reference self potential -> CT_REF_CACHED.
     fused: True -> CT_FUSED (all iterations in one launch), "tiny" -> CT_TINY (all
-    iterations in one workgroup), False -> CT_UNFUSED, None -> the library's size rule.
+    iterations in one workgroup), "mesh" -> CT_MESH (all iterations in one launch of
+    workgroups that exchange potentials without grid barriers), False -> CT_UNFUSED,
+    None -> the library's size rule.
     expanded: the lagged sweeps' exponent in the expanded form (default); False ->
     CT_DIFFERENCE (the difference form).
     static_scratch: call ct_sinkhorn_grad_static (the library's static device

@@ -169,17 +169,19 @@ hipError_t launch_fused(int d, const FusedLaunch& L, int nblocks, hipStream_t s)
 // One-workgroup solve of a small problem with everything in LDS (tiny.hip).
 constexpr int kTinyThreads = 1024;                 // 16 waves
 constexpr int kTinyWaves = kTinyThreads / 64;
-constexpr size_t kTinyMaxLds = size_t(64) << 10;   // bytes of LDS the solve may take
-// One soft-min job of a half-iteration, as LDS offsets (in floats).
+constexpr size_t kTinyMaxLds = size_t(160) << 10;  // bytes of LDS the solve may take (also
+                                                   // capped by the device's per-block limit)
+// One soft-min job of a half-iteration.  Offsets are in float4 units for record
+// arrays and in float units for everything else.
 struct TinyJob {
     int rows, keys;        // query rows, key points
-    int qc, kc;            // coordinates of rows / keys (float4 each)
-    int kh;                // key terms h_j = log2 mass_j + kappa * pot_j of the keys
+    int qrec, krec;        // record arrays of the rows / keys ([2][n] ping-pong for self jobs)
+    int out_rec;           // record array whose .w takes the rows' new key terms
+    int qnorm;             // |q'|^2 of the rows
     int qpot;              // current potential of the rows (shift, averaging)
-    int out_h;             // key terms of the rows, rewritten from the new potential
     int qlw;               // log2 mass of the rows, or -1: the constant log2a
-    int avg;               // 1: new = (old + T)/2 (self problems; key terms ping-pong)
-    int groups, splits, kps;  // 64-row groups, key ranges, keys per range
+    int avg;               // 1: new = (old + T)/2 (self problems; records ping-pong)
+    int groups, splits, kps;  // 64R-row groups, key ranges, keys per range
     int task0;             // first task index of the job within its half-iteration
 };
 struct TinyArgs {
@@ -193,17 +195,90 @@ struct TinyArgs {
     float4* yrec_q;        // [M] records of y: h from q
     unsigned* rescued;
     int T, M, d, iters, lagged0, safe_only, debias, ref_iter;
+    int R;                 // query rows per lane
     float kappa, inv_kappa, log2a;
     TinyJob job[2][2];     // [half-iteration][job]
     int njobs[2], ntasks[2];
-    // LDS offsets (floats)
-    int o_x, o_y, o_lb, o_f, o_g, o_p, o_q, o_hf, o_hg, o_hp, o_hq, o_ps, o_pm;
+    // LDS offsets: record arrays (float4 units), then floats
+    int o_rf, o_rg, o_rp, o_rq;
+    int o_f, o_g, o_p, o_q, o_lb, o_nx, o_ny, o_ps, o_pm;
     int ntask_max;
+    double est_cycles;     // the plan's modelled cycles per iteration
 };
-// Plans the tasks and the LDS layout (fills everything but the pointers and the
-// iteration options); false if the layout exceeds kTinyMaxLds.
-bool tiny_plan(int T, int M, int d, bool debias, bool ref_iter, TinyArgs& A, size_t& lds_bytes);
+// Plans the tasks, the rows per lane (r_force: 1, 2 or 4, or 0 for the cost
+// model's choice) and the LDS layout (fills everything but the pointers and the
+// iteration options); false if no plan fits in lds_cap bytes.
+bool tiny_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, int r_force,
+               TinyArgs& A, size_t& lds_bytes);
 hipError_t launch_tiny(int d, const TinyArgs& A, size_t lds_bytes, hipStream_t s);
+
+// Several workgroups, each holding every point in LDS and owning at most 64 rows
+// of each point set, exchanging their rows' potentials through versioned words
+// in global memory instead of grid barriers (mesh.hip).
+constexpr int kMeshThreads = 1024;                 // 16 waves
+constexpr int kMeshWaves = kMeshThreads / 64;
+constexpr int kMeshRows = 64;                      // rows of one point set per block, at most
+constexpr int kMeshMaxBlocks = 64;
+constexpr int kMeshGatherPerThread = 4;            // words one thread gathers per half-iteration
+// One soft-min job of a half-iteration over the block's own rows.  Offsets are
+// in float4 units for record arrays and in float units for everything else;
+// row-indexed arrays are indexed by the global row.
+struct MeshJob {
+    int yside;             // rows of y (g, q) rather than of x (f, p)
+    int keys;              // key points
+    int qrec, krec;        // record arrays of the rows / keys
+    int qnorm, qpot;       // |q'|^2 and the potential of the rows
+    int avg;               // 1: new = (old + T)/2 (self problems)
+    int splits, kps;       // key ranges, keys per range
+    int task0;             // first task index of the job within its half-iteration
+    unsigned long long* xch;   // [2][rows] versioned words of the rows' new potentials
+};
+// One potential gathered into the .w of a record array at the start of a
+// half-iteration: version = iteration + lag.
+struct MeshGather {
+    const unsigned long long* xch;   // [2][n]
+    int n;                 // points
+    int rec;               // record array that takes H = h - |v'|^2
+    int norm;              // |v'|^2
+    int lw;                // log2 mass, or -1: the constant log2a
+    int lag;               // 0: the version the iteration starts from, 1: the next one
+};
+struct MeshArgs {
+    const float4* cx;      // [T] staged coordinates of x (global)
+    const float4* cy;      // [M] staged coordinates of y
+    const float* log2b;    // [M]
+    float *f, *g, *p, *q;  // starting values in, last iterates out (own rows of each block)
+    float4* xrec_f;        // [T] records of x: h from f written at the end
+    float4* yrec_g;        // [M] records of y: h from g
+    float4* xrec_p;        // [T] records of x: h from p (the final pass's current array)
+    float4* yrec_q;        // [M] records of y: h from q
+    unsigned long long *xch_f, *xch_g, *xch_p, *xch_q;   // [2][T], [2][M], [2][T], [2][M]
+    unsigned* rescued;
+    unsigned* expired;     // set when a gather gave up waiting
+    unsigned polls;        // poll bound of one gathered word
+    unsigned version_extra;   // added to the awaited versions (0; a test hook makes waits unsatisfiable)
+    int T, M, d, iters, lagged0, safe_only, debias, ref_iter;
+    int xr, yr;            // own rows per block of x and of y
+    float kappa, inv_kappa, log2a;
+    MeshJob job[2][2];     // [half-iteration][job]
+    int njobs[2], ntasks[2];
+    MeshGather gat[2][2];
+    int ngat[2];
+    // LDS offsets: record arrays (float4 units), then floats
+    int o_rf, o_rg, o_rp, o_rq;
+    int o_f, o_g, o_p, o_q, o_lb, o_nx, o_ny, o_ps, o_pm;
+    int ntask_max;
+    double est_cycles;     // the plan's modelled cycles per iteration (compute only)
+};
+// Plans blocks, tasks and the LDS layout (fills everything but the pointers and
+// the iteration options); false if the problem needs a single block, more than
+// kMeshMaxBlocks blocks, or more than lds_cap bytes of LDS per block.  Returns
+// the grid size in *blocks.
+bool mesh_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, MeshArgs& A,
+               size_t& lds_bytes, int* blocks);
+// Blocks of k_mesh that fit on the device at once with this much LDS each.
+int mesh_resident_blocks(int d, size_t lds_bytes);
+hipError_t launch_mesh(int d, const MeshArgs& A, size_t lds_bytes, int blocks, hipStream_t s);
 
 // Per-launch event timing (ct_profile_enable); no-ops when disabled.
 bool profiling();

@@ -291,9 +291,10 @@ ct_status plan_validate(const ct_plan_problem* p, const ct_plan_opts* o, const f
     if (!o->Q || !o->R) return fail(CT_E_ARG, "Q and R must be non-null");
     if (o->flow == CT_FLOW_SINKHORN) {
         if (!y || M < 1) return fail(CT_E_ARG, "the Sinkhorn flow needs reference samples");
-        if (o->sk.flags & ~(uint32_t)(CT_DEBIAS | CT_SAFE_LSE | CT_FUSED | CT_UNFUSED | CT_TINY))
+        if (o->sk.flags &
+            ~(uint32_t)(CT_DEBIAS | CT_SAFE_LSE | CT_FUSED | CT_UNFUSED | CT_TINY | CT_MESH))
             return fail(CT_E_ARG, "plan accepts only the CT_DEBIAS, CT_SAFE_LSE, CT_FUSED, "
-                                  "CT_UNFUSED and CT_TINY Sinkhorn flags");
+                                  "CT_UNFUSED, CT_TINY and CT_MESH Sinkhorn flags");
     } else if (o->flow == CT_FLOW_SVGD) {
         if (!q) return fail(CT_E_ARG, "the Stein flow needs a mixture");
     } else if (o->flow == CT_FLOW_SVGD_GRID) {

@@ -23,6 +23,12 @@ __global__ __launch_bounds__(256) void k_zero3(unsigned* a, int na, unsigned* b,
     if (c && i < nc) c[i] = 0u;
 }
 
+// Fill 64-bit words with all ones (a version no exchange ever awaits).
+__global__ __launch_bounds__(256) void k_fill_ones64(unsigned long long* a, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = ~0ull;
+}
+
 // Sum of the reference weights in double, fixed order (one block).
 __global__ __launch_bounds__(1024) void k_wsum(const float* __restrict__ w, int M,
                                                double* __restrict__ out) {
@@ -286,6 +292,7 @@ struct SkLayout {
     unsigned* tick[3];
     size_t ntick;
     unsigned* bar;           // [kFusedBarWords] barrier words of the fused solve
+    unsigned long long* xch; // [2 (2T + 2M)] versioned potential words of the exchange solve
     size_t bytes;
 };
 
@@ -321,13 +328,14 @@ static SkLayout sk_layout(void* ws, int T, int M, int d) {
     L.ntick = std::max(job_tickets_max(T), job_tickets_max(M));
     for (int i = 0; i < 3; ++i) L.tick[i] = a.take<unsigned>(L.ntick);
     L.bar = a.take<unsigned>(kFusedBarWords);
+    L.xch = a.take<unsigned long long>(4 * ((size_t)T + M));
     L.bytes = a.off + 256;
     return L;
 }
 
 static const uint32_t kKnownFlags = CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_WARM_START |
                                     CT_REF_CACHED | CT_SAFE_LSE | CT_ONE_STREAM | CT_FUSED |
-                                    CT_UNFUSED | CT_DIFFERENCE | CT_TINY;
+                                    CT_UNFUSED | CT_DIFFERENCE | CT_TINY | CT_MESH;
 
 static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
                           const ct_sinkhorn_opts* o) {
@@ -342,9 +350,9 @@ static ct_status validate(const float* x, int64_t T, const float* y, int64_t M,
     if (o->iters < 0) return fail(CT_E_ARG, "iters must be >= 0");
     if (o->flags & ~kKnownFlags) return fail(CT_E_ARG, "unknown flag bits 0x%x", o->flags & ~kKnownFlags);
     {
-        const uint32_t ex = o->flags & (CT_FUSED | CT_UNFUSED | CT_TINY);
+        const uint32_t ex = o->flags & (CT_FUSED | CT_UNFUSED | CT_TINY | CT_MESH);
         if (ex & (ex - 1))
-            return fail(CT_E_ARG, "CT_FUSED, CT_UNFUSED and CT_TINY exclude each other");
+            return fail(CT_E_ARG, "CT_FUSED, CT_UNFUSED, CT_TINY and CT_MESH exclude each other");
     }
     if (!x || !y) return fail(CT_E_ARG, "x and y must be non-null");
     return CT_OK;
@@ -561,14 +569,13 @@ static ct_status run_fused(const SkLayout& L, const SkConsts& c, const SkJobs& J
 }
 
 // One-workgroup solve (all K iterations in one workgroup, everything in LDS; see
-// tiny.hip).  By default it is taken when one iteration has at most
-// kTinyAutoPairs point pairs and the problem fits in the LDS a workgroup may
-// take: one compute unit evaluates such an iteration faster than the GPU can
-// synchronise across its dies (measured on an MI355X, K = 100, d = 3: 0.72 ms at
-// T = M = 100 against 1.24 for the fused solve and 1.39 for per-sweep launches;
-// even with the fused solve at T = M = 200; behind it from 300 on).  CT_TINY
-// forces it (CT_E_UNSUPPORTED when the problem does not fit); CT_FUSED and
-// CT_UNFUSED rule it out.
+// tiny.hip).  By default it is taken, where the exchange solve is not, when one
+// iteration has at most kTinyAutoPairs point pairs and the problem fits in the
+// LDS a workgroup may take: one compute unit evaluates such an iteration faster
+// than the GPU can synchronise across its dies (measured on an MI355X, K = 100,
+// d = 3, whole call: 0.59 ms at T = M = 100 against 1.34 for the fused solve and
+// 1.41 for per-sweep launches).  CT_TINY forces it (CT_E_UNSUPPORTED when the
+// problem does not fit); CT_FUSED, CT_UNFUSED and CT_MESH rule it out.
 constexpr double kTinyAutoPairs = 150000.0;
 
 static size_t device_max_lds() {
@@ -596,11 +603,17 @@ static ct_status run_tiny(const SkLayout& L, const SkConsts& c, const ct_sinkhor
     if (!forced && pairs > kTinyAutoPairs) return CT_OK;
     TinyArgs A;
     size_t lds = 0;
-    if (!tiny_plan(T, M, d, debias, ref_iter, A, lds) || lds > device_max_lds()) {
+    const size_t cap = std::min(kTinyMaxLds, device_max_lds());
+    // test and tuning hook: query rows per lane (1, 2 or 4) instead of the cost model's choice
+    int r_force = 0;
+    if (const char* e = std::getenv("CT_TINY_R")) {
+        r_force = std::atoi(e);
+        if (r_force != 1 && r_force != 2 && r_force != 4) r_force = 0;
+    }
+    if (!tiny_plan(T, M, d, debias, ref_iter, cap, r_force, A, lds)) {
         if (forced)
             return fail(CT_E_UNSUPPORTED, "T=%d, M=%d needs %zu bytes of LDS; the one-workgroup "
-                                          "solve may take %zu", T, M, lds,
-                        std::min(kTinyMaxLds, device_max_lds()));
+                                          "solve may take %zu", T, M, lds, cap);
         return CT_OK;
     }
     const int cur = o->iters & 1;   // the self record arrays current after K iterations
@@ -628,6 +641,89 @@ static ct_status run_tiny(const SkLayout& L, const SkConsts& c, const ct_sinkhor
     return CT_OK;
 }
 
+// Multi-workgroup exchange solve (all K iterations in one launch of blocks that
+// each hold every point in LDS and own at most 64 rows of each point set; see
+// mesh.hip).  By default it is taken when it plans (two or more blocks, every
+// point in one block's LDS, all blocks resident at once), one iteration has more
+// than kMeshMinPairs point pairs (below that the one-workgroup solve is as fast)
+// and at most kMeshAutoPairs.  Measured on an MI355X, K = 100, d = 3, T = M,
+// cached reference potential, whole call (exchange / one-workgroup / fused /
+// per-sweep launches): T = 100: 0.63 / 0.59 / 1.34 / 1.41 ms; 300: 0.87 / 1.94 /
+// 1.87 / 2.26; 500: 1.08 / 3.65 / 2.63 / 2.66; 1000: 1.54 / - / 7.0 / 2.70;
+// 2000: 2.57 / - / 23.5 / 3.13.  CT_MESH forces it (CT_E_UNSUPPORTED when it
+// cannot plan); CT_FUSED, CT_UNFUSED and CT_TINY rule it out.
+constexpr double kMeshMinPairs = 40000.0;
+constexpr double kMeshAutoPairs = 2.0e7;
+constexpr unsigned kMeshWaitPolls = 1u << 18;
+
+static ct_status run_mesh(const SkLayout& L, const SkConsts& c, const ct_sinkhorn_opts* o,
+                          bool debias, bool ref_iter, bool warm, bool safe_only, hipStream_t st,
+                          bool* ran) {
+    *ran = false;
+    const int T = c.T, M = c.M, d = c.d;
+    const bool forced = o->flags & CT_MESH;
+    const double pairs = 2.0 * T * M + (debias ? (double)T * T : 0.0) +
+                         (ref_iter ? (double)M * M : 0.0);
+    if (!forced && (pairs > kMeshAutoPairs || pairs <= kMeshMinPairs)) return CT_OK;
+    MeshArgs A;
+    size_t lds = 0;
+    int blocks = 0;
+    const size_t cap = std::min(kTinyMaxLds, device_max_lds());
+    const bool planned = mesh_plan(T, M, d, debias, ref_iter, cap, A, lds, &blocks);
+    if (!planned || blocks > mesh_resident_blocks(d, lds)) {
+        if (forced)
+            return fail(CT_E_UNSUPPORTED, "the exchange solve has no plan for T=%d, M=%d (it needs "
+                                          "2 to %d blocks of at most %d rows and every point in "
+                                          "%zu bytes of LDS)", T, M, kMeshMaxBlocks, kMeshRows, cap);
+        return CT_OK;
+    }
+    const int cur = o->iters & 1;   // the self record arrays current after K iterations
+    A.cx = L.cx;
+    A.cy = L.cy;
+    A.log2b = L.log2b;
+    A.f = L.f;
+    A.g = L.g;
+    A.p = L.p;
+    A.q = L.q;
+    A.xrec_f = L.xrec[0];
+    A.yrec_g = L.yrec[0];
+    A.xrec_p = L.xrec[2 + cur];
+    A.yrec_q = L.yrec[1 + cur];
+    A.xch_f = L.xch;
+    A.xch_p = L.xch + 2 * (size_t)T;
+    A.xch_g = L.xch + 4 * (size_t)T;
+    A.xch_q = L.xch + 4 * (size_t)T + 2 * (size_t)M;
+    for (int h = 0; h < 2; ++h) {
+        for (int j = 0; j < A.njobs[h]; ++j) {
+            MeshJob& J = A.job[h][j];
+            J.xch = J.yside ? (J.avg ? A.xch_q : A.xch_g) : (J.avg ? A.xch_p : A.xch_f);
+        }
+    }
+    A.gat[0][0].xch = A.xch_g;
+    if (A.ngat[0] > 1) A.gat[0][1].xch = A.xch_p;
+    A.gat[1][0].xch = A.xch_f;
+    if (A.ngat[1] > 1) A.gat[1][1].xch = A.xch_q;
+    A.rescued = L.counters + 1;
+    A.expired = L.counters + 4;
+    A.polls = kMeshWaitPolls;
+    // test hooks of the give-up path: a poll bound, and waits that no version satisfies
+    if (const char* e = std::getenv("CT_MESH_WAIT_POLLS")) A.polls = (unsigned)std::strtoul(e, nullptr, 10);
+    if (const char* e = std::getenv("CT_MESH_UNSATISFIABLE_WAITS")) A.version_extra = std::atoi(e) ? (1u << 20) : 0u;
+    A.d = d;
+    A.iters = o->iters;
+    A.lagged0 = warm ? 1 : 0;
+    A.safe_only = safe_only ? 1 : 0;
+    A.kappa = c.kappa;
+    A.inv_kappa = c.inv_kappa;
+    A.log2a = c.log2a;
+    const int nw = 4 * (T + M);
+    hipLaunchKernelGGL(k_fill_ones64, dim3((nw + 255) / 256), dim3(256), 0, st, L.xch, nw);
+    CT_CHECK_HIP(hipGetLastError());
+    CT_CHECK_HIP(launch_mesh(d, A, lds, blocks, st));
+    *ran = true;
+    return CT_OK;
+}
+
 // Iterate-and-extrapolate for one problem whose arrays are staged in L.
 static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_opts* o,
                              hipStream_t st, const ForkJoin* fj) {
@@ -646,11 +742,15 @@ static ct_status run_problem(const SkLayout& L, int T, int M, const ct_sinkhorn_
     int cur = 0;  // which ping-pong self record array is current
     bool fused = false;
     if (o->iters > 0 && !(o->flags & CT_UNFUSED)) {
-        if (!(o->flags & CT_FUSED)) {
+        if (!(o->flags & (CT_FUSED | CT_TINY))) {
+            ct_status rc = run_mesh(L, c, o, debias, ref_iter, warm, safe_only, st, &fused);
+            if (rc) return rc;
+        }
+        if (!fused && !(o->flags & (CT_FUSED | CT_MESH))) {
             ct_status rc = run_tiny(L, c, o, debias, ref_iter, warm, safe_only, st, &fused);
             if (rc) return rc;
         }
-        if (!fused && !(o->flags & CT_TINY)) {
+        if (!fused && !(o->flags & (CT_TINY | CT_MESH))) {
             ct_status rc = run_fused(L, c, J, o, debias, ref_iter, warm, safe_only, st, &fused);
             if (rc) return rc;
         }
@@ -1077,8 +1177,8 @@ extern "C" ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* n
     if (rescued) *rescued = c[1];
     if (resid) *resid = r;
     if (c[4])
-        return fail(CT_E_DEVICE, "a grid barrier of the last call's fused solve gave up: its "
-                                 "outputs are not valid");
+        return fail(CT_E_DEVICE, "a wait of the last call's fused or exchange solve gave up: "
+                                 "its outputs are not valid");
     if (c[0])
         return fail(CT_E_NONFINITE, "the last gradient call saw %u non-finite coordinates or "
                                     "non-positive weights: its outputs are not valid", c[0]);

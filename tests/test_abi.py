@@ -53,10 +53,13 @@ def test_sinkhorn_rejects_bad_arguments_before_launch():
     assert _call_sinkhorn(o=O(2, 10, 0.0, 1)) == _lib.CT_E_ARG
     assert _call_sinkhorn(o=O(2, 10, float("nan"), 1)) == _lib.CT_E_ARG
     assert _call_sinkhorn(o=O(2, -1, 0.01, 1)) == _lib.CT_E_ARG
-    assert _call_sinkhorn(o=O(2, 10, 0.01, 1 << 12)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, 10, 0.01, 1 << 20)) == _lib.CT_E_ARG
     assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_FUSED | _lib.CT_UNFUSED)) == _lib.CT_E_ARG
     assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_TINY | _lib.CT_FUSED)) == _lib.CT_E_ARG
     assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_TINY | _lib.CT_UNFUSED)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_MESH | _lib.CT_TINY)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_MESH | _lib.CT_FUSED)) == _lib.CT_E_ARG
+    assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_MESH | _lib.CT_UNFUSED)) == _lib.CT_E_ARG
     assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_GRAD_W)) == _lib.CT_E_ARG   # grad_w missing
     assert _call_sinkhorn(o=O(2, 10, 0.01, _lib.CT_WARM_START)) == _lib.CT_E_ARG  # pot missing
     assert _call_sinkhorn(gx=None) == _lib.CT_E_ARG

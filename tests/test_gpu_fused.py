@@ -182,6 +182,24 @@ def test_one_workgroup_matches_oracle(ct, d, T, M, eps, iters):
     assert max(e.values()) < TOL, e
 
 
+@pytest.mark.parametrize("rows_per_lane", [1, 2, 4])
+@pytest.mark.parametrize("d,T,M", [(3, 150, 97), (2, 300, 260)])
+def test_one_workgroup_every_rows_per_lane_matches_oracle(ct, monkeypatch, rows_per_lane, d, T, M):
+    """Each plan shape of the one-workgroup solve (1, 2 or 4 query rows per lane,
+    forced through the CT_TINY_R hook) on ragged sizes: row groups with a partial
+    last group, key ranges with a short last range."""
+    monkeypatch.setenv("CT_TINY_R", str(rows_per_lane))
+    cfg = W.CONFIGS["grad_2d"] if d == 2 else W.CONFIGS["autograd_3d"]
+    x, y, w, _g = W.config_inputs(cfg, T=T, M=M)
+    w = W.positive_weights(np.random.default_rng(T + M), M)
+    print(f"one-workgroup R={rows_per_lane} d={d} T={T} M={M}", flush=True)
+    g = _run(ct, x, y, w, 0.01, 40, fused="tiny")
+    r = oracle.sinkhorn(x, y, w, eps=0.01, iters=40)
+    e = _errs(g, r, T, M, w)
+    print(" ".join(f"{k}={v:.2e}" for k, v in e.items()))
+    assert max(e.values()) < TOL, e
+
+
 def test_one_workgroup_agrees_with_other_executions_and_is_deterministic(ct):
     x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=300, M=700)
     w = W.positive_weights(np.random.default_rng(5), 700)
