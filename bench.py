@@ -65,9 +65,11 @@ STEIN_MIX = {"add": 3.0, "fma": 5.0, "exp": 1.0}
 
 
 def sweep_source_hash() -> str:
+    """Hash of what decides the sweeps' memory traffic: their sources and the stored
+    schedule table (queries per lane, key splits, blocks, merge mode)."""
     h = hashlib.sha256()
-    for f in ("sweep_device.h", "sweep.hip"):
-        with open(os.path.join(ROOT, "paper_2511_11514_amd", "csrc", f), "rb") as fh:
+    for f in (("csrc", "sweep_device.h"), ("csrc", "sweep.hip"), ("tuning", "mi355x.txt")):
+        with open(os.path.join(ROOT, "paper_2511_11514_amd", *f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -48,10 +48,11 @@ def _fixture(name):
 @pytest.mark.parametrize("expanded", [False, True], ids=["difference", "expanded"])
 @pytest.mark.parametrize("name", ["planner_2d_full", "grad_2d_full", "autograd_3d_T4096_M16384",
                                   "roofline_2d_T4096_M16384", "autograd_3d_full"])
-def test_sinkhorn_against_stored_oracle(ct, name, expanded):
+def test_sinkhorn_against_stored_oracle(ct, stored_schedules, name, expanded):
     """Each stored workload through the default execution (whose per-sweep launches
     use the expanded exponent), and through the per-sweep launches with the
-    difference form (CT_DIFFERENCE)."""
+    difference form (CT_DIFFERENCE), with the stored MI355X schedules (the launch
+    configuration the benchmark times)."""
     F = _fixture(name)
     cfg = W.CONFIGS[str(F["workload"])]
     T, M, K = int(F["T"]), int(F["M"]), int(F["iters"])
