@@ -330,6 +330,9 @@ def main() -> int:
     ap.add_argument("--stein-only", action="store_true",
                     help="instead of the benchmark line: only the Stein leg (T = 65536), for "
                          "profiling its median and sum kernels")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="instead of the benchmark line: only the batched leg (256 uneven "
+                         "problems), for profiling its launches")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -378,6 +381,9 @@ def main() -> int:
     if args.grad_2d_only:
         print(json.dumps(grad_2d_leg(ct, torch, dev, L, _lib, tuned, steps=args.steps,
                                      warmup=args.warmup, graph=args.graph)))
+        return 0
+    if args.batched_only:
+        print(json.dumps(batched_leg(ct, torch, dev, reps=max(1, args.steps))))
         return 0
 
     # headline: one gradient pass of the large 2-D workload (unicycle trajectory
