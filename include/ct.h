@@ -238,17 +238,31 @@ ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* nonfinite, u
 
 /*
  * Many independent problems b = 0..B-1 of uneven size (the batched form of
- * ct_sinkhorn_grad, same definitions and options for every problem).  Default:
- * lockstep launches, two per iteration (every problem's f and self updates, then
- * every problem's g update) over job tables prepared in the workspace, each job
- * split over keys so that all blocks sweep about the same number of pairs.  With
- * CT_PERSISTENT: one persistent kernel that walks a dependency-ordered work list.
+ * ct_sinkhorn_grad, same definitions and options for every problem).  Three
+ * executions of the K iterations:
+ *   exchange (CT_MESH; the default when it applies): one launch for the whole
+ *     batch, each problem given the blocks of its exchange solve (see CT_MESH:
+ *     every point of the problem in each block's LDS, at most 64 own rows of x and
+ *     of y per block, potentials passed between the problem's blocks as versioned
+ *     words); it applies when every problem has at most 2e7 point pairs per
+ *     iteration and fits one workgroup's LDS and all the blocks fit on the device
+ *     at once (decided by ct_sinkhorn_batched_prepare; CT_E_UNSUPPORTED there for
+ *     CT_MESH when it does not apply);
+ *   lockstep (CT_UNFUSED, and the default otherwise): two launches per iteration
+ *     (every problem's f and self updates, then every problem's g update) over
+ *     job tables prepared in the workspace, each job split over keys so that all
+ *     blocks sweep about the same number of pairs;
+ *   persistent (CT_PERSISTENT): one kernel that walks a dependency-ordered work
+ *     list.
+ * The extrapolation pass and the reductions follow as lockstep launches in every
+ * execution.
  *   T_off, M_off  host [B+1]  prefix offsets: problem b owns x rows
  *                             T_off[b]..T_off[b+1]-1 and y rows M_off[b]..M_off[b+1]-1
  *                             (every problem needs T_b >= 1, M_b >= 1)
  *   x, y, w, grad_x, grad_w   concatenations in that order (w may be NULL)
  *   value         device [B] or NULL (requires CT_VALUE)
- * Flags: CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_SAFE_LSE, CT_PERSISTENT, CT_DIFFERENCE (others:
+ * Flags: CT_DEBIAS, CT_GRAD_W, CT_VALUE, CT_SAFE_LSE, CT_PERSISTENT, CT_MESH, CT_UNFUSED
+ * (at most one of the last three), CT_DIFFERENCE (others:
  * CT_E_ARG).
  * The workspace must first be prepared for this batch (same B, offsets, d, iters,
  * flags) by ct_sinkhorn_batched_prepare, which builds the work list on the host
@@ -261,7 +275,12 @@ ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* nonfinite, u
  * turns such an error into a result instead of a hang), every grad_x, grad_w and
  * value entry of the call is NaN.  The environment variable
  * CT_PERSISTENT_WAIT_POLLS, read at each call, replaces the bound (0: a wait
- * expires at its first unsatisfied poll), to test that path.
+ * expires at its first unsatisfied poll), to test that path.  The exchange
+ * execution's waits are bounded likewise (2^18 polls per word) with the same
+ * outcome; CT_MESH_WAIT_POLLS and CT_MESH_UNSATISFIABLE_WAITS, read when the batch
+ * is prepared, replace the bound and make every wait unsatisfiable, to test that
+ * path.  The exchange execution's tables hold kappa: a call with another eps than
+ * the prepared one returns CT_E_ARG.
  */
 size_t ct_sinkhorn_batched_workspace_size(int32_t B, const int64_t* T_off, const int64_t* M_off,
                                           const ct_sinkhorn_opts* o);

@@ -198,14 +198,30 @@ class BatchedOut:
     value: Optional[torch.Tensor]
 
 
+def _batched_mode_flag(mode, persistent: bool) -> int:
+    """None: the library's rule (the exchange solve when it applies, else lockstep
+    launches); "lockstep" -> CT_UNFUSED; "persistent" (or persistent=True) ->
+    CT_PERSISTENT; "mesh" -> CT_MESH."""
+    if persistent:
+        if mode not in (None, "persistent"):
+            raise ValueError("persistent=True conflicts with mode=%r" % (mode,))
+        return L.CT_PERSISTENT
+    table = {None: 0, "lockstep": L.CT_UNFUSED, "persistent": L.CT_PERSISTENT, "mesh": L.CT_MESH}
+    if mode not in table:
+        raise ValueError(f"mode must be None, 'lockstep', 'persistent' or 'mesh' (got {mode!r})")
+    return table[mode]
+
+
 def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor],
                           ws: Optional[Sequence[torch.Tensor]] = None, *, eps: float, iters: int,
                           debias: bool = True, value: bool = False, grad_w: bool = False,
                           safe: bool = False, persistent: bool = False,
-                          expanded: bool = True) -> BatchedOut:
-    """Many independent problems (ragged T_b, M_b): lockstep launches over all of
-    them (default) or one persistent launch (persistent=True).  expanded: as for
-    sinkhorn_grad (the lockstep launches' lagged sweeps)."""
+                          expanded: bool = True, mode: Optional[str] = None) -> BatchedOut:
+    """Many independent problems (ragged T_b, M_b) in one batch: by default the
+    exchange solve in one launch when every problem fits it, else lockstep
+    launches over all of them; mode "lockstep", "persistent" (or persistent=True:
+    one persistent work-list launch) or "mesh" forces one execution.  expanded: as
+    for sinkhorn_grad (the lockstep launches' lagged sweeps)."""
     B = len(xs)
     if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
         raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
@@ -221,7 +237,7 @@ def sinkhorn_grad_batched(xs: Sequence[torch.Tensor], ys: Sequence[torch.Tensor]
     w = None if ws is None else _req(torch.cat([_req(t, "w", dev) for t in ws]), "w")
     flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
         (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
-        (L.CT_PERSISTENT if persistent else 0) | (0 if expanded else L.CT_DIFFERENCE)
+        _batched_mode_flag(mode, persistent) | (0 if expanded else L.CT_DIFFERENCE)
     o = _opts(d, eps, iters, flags)
     to = T_off.ctypes.data_as(L.PI64)
     mo = M_off.ctypes.data_as(L.PI64)
@@ -247,7 +263,7 @@ class BatchedSinkhorn:
 
     def __init__(self, xs, ys, ws=None, *, eps: float, iters: int, debias: bool = True,
                  value: bool = False, grad_w: bool = False, safe: bool = False,
-                 persistent: bool = False, expanded: bool = True):
+                 persistent: bool = False, expanded: bool = True, mode: Optional[str] = None):
         B = len(xs)
         if B < 1 or len(ys) != B or (ws is not None and len(ws) != B):
             raise ValueError("xs, ys (and ws) must be non-empty lists of equal length")
@@ -264,7 +280,7 @@ class BatchedSinkhorn:
         self.w = None if ws is None else _req(torch.cat([_req(t, "w", self.dev) for t in ws]), "w")
         flags = (L.CT_DEBIAS if debias else 0) | (L.CT_VALUE if value else 0) | \
             (L.CT_GRAD_W if grad_w else 0) | (L.CT_SAFE_LSE if safe else 0) | \
-            (L.CT_PERSISTENT if persistent else 0) | (0 if expanded else L.CT_DIFFERENCE)
+            _batched_mode_flag(mode, persistent) | (0 if expanded else L.CT_DIFFERENCE)
         self.o = _opts(self.d, eps, iters, flags)
         self._to = self.T_off.ctypes.data_as(L.PI64)
         self._mo = self.M_off.ctypes.data_as(L.PI64)

@@ -8,7 +8,12 @@
 //    split over keys so that all blocks of a launch sweep about the same number
 //    of pairs (lockstep.hip), split jobs merged by a second kernel;
 //  * persistent (CT_PERSISTENT): one launch walking a dependency-ordered work
-//    list, described next.
+//    list, described next;
+//  * exchange (CT_MESH, and by default whenever every problem's points fit in
+//    one workgroup's LDS and all their blocks fit on the device at once): one
+//    launch of the exchange solve of mesh.hip for every problem (each problem's
+//    blocks pass their rows' potentials to each other as versioned words), then
+//    the lockstep extrapolation launches.
 //
 // Work list.  Every problem runs the same stage sequence
 //     A_0, B_0, A_1, B_1, ..., A_{K-1}, B_{K-1}, F1, F2
@@ -99,6 +104,8 @@ struct BLayout {
     Job* ljobs;             // [kLockKinds][3B] lockstep job tables
     int* lblk;              // [kLockKinds][3B] sweep-block prefix ends
     int* lmrg;              // [kLockKinds][3B] merge-block prefix ends
+    MeshArgs* mtab;         // [B] exchange-solve arguments per problem
+    int* mblk;              // [B] exchange-solve block prefix ends
     float* lpart;           // partial sums of split lockstep jobs (one launch at a time)
     unsigned* done;         // [B] completed units per problem
     unsigned* head;         // [1] next unit
@@ -111,8 +118,9 @@ struct BLayout {
     float *b, *log2b;
     float *f, *g, *p, *q, *fp, *gp, *pp, *qp;
     float *dy, *ds;
+    unsigned long long* xch;   // [4 (sumT + sumM)] versioned words of the exchange solve
     size_t bytes;
-    size_t table_bytes;     // bytes of the host-built table (header .. yoff)
+    size_t table_bytes;     // bytes of the host-built table (header .. mblk)
 };
 
 static BLayout b_layout(void* ws, int B, int64_t sumT, int64_t sumM, int64_t sumTpad,
@@ -131,6 +139,8 @@ static BLayout b_layout(void* ws, int B, int64_t sumT, int64_t sumM, int64_t sum
     L.ljobs = a.take<Job>((size_t)kLockKinds * 3 * B);
     L.lblk = a.take<int>((size_t)kLockKinds * 3 * B);
     L.lmrg = a.take<int>((size_t)kLockKinds * 3 * B);
+    L.mtab = a.take<MeshArgs>(B);
+    L.mblk = a.take<int>(B);
     L.table_bytes = a.off;
     L.lpart = a.take<float>(part_floats);
     L.done = a.take<unsigned>(B);
@@ -154,6 +164,7 @@ static BLayout b_layout(void* ws, int B, int64_t sumT, int64_t sumM, int64_t sum
     L.qp = a.take<float>(sumM);
     L.dy = a.take<float>((size_t)sumT * d);
     L.ds = a.take<float>((size_t)sumT * d);
+    L.xch = a.take<unsigned long long>(4 * ((size_t)sumT + sumM));
     L.bytes = a.off + 256;
     return L;
 }
@@ -521,9 +532,16 @@ __global__ __launch_bounds__(256) void k_breduce(BLayout L, float kappa, float* 
 namespace {
 
 std::mutex g_prep_mu;
+struct MeshInfo {
+    int blocks;             // 0: no exchange solve (lockstep or persistent launches)
+    size_t lds;             // dynamic LDS of the launch (the largest problem's)
+    double pairs;           // point pairs of its iterations
+    float eps;              // the eps its tables were built for
+};
 struct Prepared {
     unsigned long long signature;
     LockInfo lock;
+    MeshInfo mesh;
 };
 std::map<const void*, Prepared> g_prepared;   // workspace -> what it was prepared for
 
@@ -561,8 +579,13 @@ ct_status b_validate(int B, const int64_t* To, const int64_t* Mo, const ct_sinkh
     if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(CT_E_ARG, "eps must be finite and > 0");
     if (o->iters < 0) return fail(CT_E_ARG, "iters must be >= 0");
     if (o->flags & ~(uint32_t)(CT_DEBIAS | CT_GRAD_W | CT_VALUE | CT_SAFE_LSE | CT_PERSISTENT |
-                               CT_DIFFERENCE))
+                               CT_DIFFERENCE | CT_MESH | CT_UNFUSED))
         return fail(CT_E_ARG, "unsupported flags for the batched path");
+    {
+        const uint32_t ex = o->flags & (CT_PERSISTENT | CT_MESH | CT_UNFUSED);
+        if (ex & (ex - 1))
+            return fail(CT_E_ARG, "CT_PERSISTENT, CT_MESH and CT_UNFUSED exclude each other");
+    }
     if (To[0] != 0 || Mo[0] != 0) return fail(CT_E_SHAPE, "offsets must start at 0");
     S = BatchSizes{0, 0, 0, 0};
     for (int b = 0; b < B; ++b) {
@@ -708,6 +731,101 @@ size_t build_lock(const BLayout& L, const std::vector<BProb>& P, uint32_t flags,
     return part_max;
 }
 
+// Exchange solve of the whole batch: every problem planned (one block allowed),
+// at most kMeshBatchPairs point pairs per iteration each, all blocks resident at
+// once.  Fills tab/blk (device pointers of L) and returns false if it does not
+// apply.
+constexpr double kMeshBatchPairs = 2.0e7;
+constexpr unsigned kMeshBatchWaitPolls = 1u << 18;
+
+size_t device_lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    return (size_t)std::max(0, v);
+}
+
+bool plan_mesh_batch(const BLayout& L, const std::vector<BProb>& P, const ct_sinkhorn_opts* o,
+                     MeshArgs* tab, int* blk, MeshInfo& info) {
+    info = MeshInfo{0, 0, 0.0, o->eps};
+    const int B = (int)P.size(), d = o->d;
+    const bool debias = o->flags & CT_DEBIAS;
+    const bool want_v = o->flags & (CT_VALUE | CT_GRAD_W);
+    const bool need_ref = debias && want_v;
+    const size_t dev_lds = device_lds_per_block();
+    if (dev_lds <= sizeof(MeshArgs)) return false;
+    const size_t cap = std::min(kTinyMaxLds, dev_lds) - sizeof(MeshArgs);
+    const double kappa_d = kLog2e / (double)o->eps;
+    const int curF = o->iters & 1;
+    unsigned polls = kMeshBatchWaitPolls, extra = 0u;
+    // test hooks of the give-up path (read when the batch is prepared)
+    if (const char* e = std::getenv("CT_MESH_WAIT_POLLS")) polls = (unsigned)std::strtoul(e, nullptr, 10);
+    if (const char* e = std::getenv("CT_MESH_UNSATISFIABLE_WAITS")) extra = std::atoi(e) ? (1u << 20) : 0u;
+    int blocks = 0;
+    size_t lds_max = 0;
+    double pairs = 0.0;
+    for (int b = 0; b < B; ++b) {
+        const BProb& Q = P[b];
+        const double pp = 2.0 * Q.T * Q.M + (debias ? (double)Q.T * Q.T : 0.0) +
+                          (need_ref ? (double)Q.M * Q.M : 0.0);
+        if (pp > kMeshBatchPairs) return false;
+        MeshArgs& A = tab[b];
+        size_t lds = 0;
+        int G = 0;
+        if (!mesh_plan(Q.T, Q.M, d, debias, need_ref, cap, true, A, lds, &G)) return false;
+        A.cx = L.cx + Q.xo;
+        A.cy = L.cy + Q.yo;
+        A.log2b = L.log2b + Q.yo;
+        A.f = L.f + Q.xo;
+        A.g = L.g + Q.yo;
+        A.p = L.p + Q.xo;
+        A.q = L.q + Q.yo;
+        A.xrec_f = L.xrec[0] + Q.xp;
+        A.yrec_g = L.yrec[0] + Q.yp;
+        A.xrec_p = L.xrec[2 + curF] + Q.xp;
+        A.yrec_q = L.yrec[1 + curF] + Q.yp;
+        unsigned long long* x0 = L.xch + 4 * ((size_t)Q.xo + Q.yo);
+        A.xch_f = x0;
+        A.xch_p = x0 + 2 * (size_t)Q.T;
+        A.xch_g = x0 + 4 * (size_t)Q.T;
+        A.xch_q = x0 + 4 * (size_t)Q.T + 2 * (size_t)Q.M;
+        for (int h = 0; h < 2; ++h)
+            for (int j = 0; j < A.njobs[h]; ++j) {
+                MeshJob& J = A.job[h][j];
+                J.xch = J.yside ? (J.avg ? A.xch_q : A.xch_g) : (J.avg ? A.xch_p : A.xch_f);
+            }
+        A.gat[0][0].xch = A.xch_g;
+        if (A.ngat[0] > 1) A.gat[0][1].xch = A.xch_p;
+        A.gat[1][0].xch = A.xch_f;
+        if (A.ngat[1] > 1) A.gat[1][1].xch = A.xch_q;
+        A.rescued = L.counters + 1;
+        A.expired = L.counters + 2;   // the batched outputs' invalid flag
+        A.polls = polls;
+        A.version_extra = extra;
+        A.d = d;
+        A.iters = o->iters;
+        A.lagged0 = 0;
+        A.safe_only = (o->flags & CT_SAFE_LSE) ? 1 : 0;
+        A.kappa = (float)kappa_d;
+        A.inv_kappa = (float)(1.0 / kappa_d);
+        A.log2a = Q.log2a;
+        blocks += G;
+        blk[b] = blocks;
+        lds_max = std::max(lds_max, lds);
+        pairs += o->iters * pp;
+    }
+    if (blocks > mesh_resident_blocks(d, lds_max, true)) return false;
+    info.blocks = blocks;
+    info.lds = lds_max;
+    info.pairs = pairs;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_bfill_ones64(unsigned long long* a, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = ~0ull;
+}
+
 // Floats of lockstep partial sums for this batch (the planning does not depend
 // on where the workspace is).
 size_t lock_part_floats(int B, const int64_t* To, const int64_t* Mo, const ct_sinkhorn_opts* o,
@@ -830,11 +948,23 @@ extern "C" ct_status ct_sinkhorn_batched_prepare(int32_t B, const int64_t* To, c
     const std::vector<BProb> BP = base_probs(B, To, Mo);
     build_lock(L, BP, o->flags, o->iters, o->d, lock_schedule(o->d), H0.ljobs, H0.lblk, H0.lmrg,
                info);
+    MeshInfo minfo{0, 0, 0.0, o->eps};
+    if (!(o->flags & (CT_PERSISTENT | CT_UNFUSED)) && o->iters > 0) {
+        const bool ok = plan_mesh_batch(L, BP, o, H0.mtab, H0.mblk, minfo);
+        if (!ok) {
+            minfo = MeshInfo{0, 0, 0.0, o->eps};
+            if (o->flags & CT_MESH)
+                return fail(CT_E_UNSUPPORTED, "the exchange solve does not apply to this batch (a "
+                                              "problem above %.3g pairs per iteration or beyond one "
+                                              "workgroup's LDS, or more blocks than fit at once)",
+                            kMeshBatchPairs);
+        }
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     CT_CHECK_HIP(hipMemcpyAsync(ws, img.data(), img.size(), hipMemcpyHostToDevice, st));
     CT_CHECK_HIP(hipStreamSynchronize(st));
     std::lock_guard<std::mutex> lk(g_prep_mu);
-    g_prepared[ws] = Prepared{H.signature, info};
+    g_prepared[ws] = Prepared{H.signature, info, minfo};
     return CT_OK;
 }
 
@@ -858,6 +988,7 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
     if (ws_bytes < L.bytes) return fail(CT_E_WORKSPACE, "workspace too small: %zu < %zu", ws_bytes, L.bytes);
     const Schedule sc = batched_schedule(o->d);
     LockInfo info;
+    MeshInfo minfo;
     {
         std::lock_guard<std::mutex> lk(g_prep_mu);
         auto it = g_prepared.find(ws);
@@ -865,7 +996,11 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
             return fail(CT_E_ARG, "workspace not prepared for this batch "
                                   "(call ct_sinkhorn_batched_prepare first)");
         info = it->second.lock;
+        minfo = it->second.mesh;
     }
+    if (minfo.blocks > 0 && minfo.eps != o->eps)
+        return fail(CT_E_ARG, "the batch's exchange-solve tables were prepared for eps=%g (got %g)",
+                    (double)minfo.eps, (double)o->eps);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const double kappa_d = kLog2e / (double)o->eps;
     hipLaunchKernelGGL(k_bwsum, dim3(B), dim3(256), 0, st, L, x, y, w, o->d);
@@ -896,8 +1031,17 @@ extern "C" ct_status ct_sinkhorn_grad_batched(int32_t B, const int64_t* To, cons
             return CT_OK;
         };
         const bool safe_only = o->flags & CT_SAFE_LSE;
+        if (minfo.blocks > 0) {
+            // the K iterations of every problem in one launch of the exchange solve
+            const int64_t nw = 4 * (S.sumT + S.sumM);
+            hipLaunchKernelGGL(k_bfill_ones64, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
+                               L.xch, nw);
+            CT_CHECK_HIP(hipGetLastError());
+            CT_CHECK_HIP(launch_mesh_batch(o->d, L.mtab, L.mblk, B, minfo.lds, minfo.blocks,
+                                           minfo.pairs, st));
+        }
         void* tok = profile_begin(st);
-        for (int k = 0; k < o->iters; ++k) {
+        for (int k = 0; k < (minfo.blocks > 0 ? 0 : o->iters); ++k) {
             const bool lagged = !safe_only && k > 0;
             rc = run_kind(k & 1, lagged, false);
             if (rc) return rc;

@@ -212,6 +212,11 @@ bool tiny_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, 
                TinyArgs& A, size_t& lds_bytes);
 hipError_t launch_tiny(int d, const TinyArgs& A, size_t lds_bytes, hipStream_t s);
 
+// Raise a kernel's dynamic-LDS limit on the current device to at least `bytes`
+// (beyond the default 64 KiB); never lowers it, so launches planned for larger
+// problems stay valid.
+hipError_t ensure_dynamic_lds(const void* fn, size_t bytes);
+
 // Several workgroups, each holding every point in LDS and owning at most 64 rows
 // of each point set, exchanging their rows' potentials through versioned words
 // in global memory instead of grid barriers (mesh.hip).
@@ -271,14 +276,20 @@ struct MeshArgs {
     double est_cycles;     // the plan's modelled cycles per iteration (compute only)
 };
 // Plans blocks, tasks and the LDS layout (fills everything but the pointers and
-// the iteration options); false if the problem needs a single block, more than
-// kMeshMaxBlocks blocks, or more than lds_cap bytes of LDS per block.  Returns
-// the grid size in *blocks.
-bool mesh_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, MeshArgs& A,
-               size_t& lds_bytes, int* blocks);
-// Blocks of k_mesh that fit on the device at once with this much LDS each.
-int mesh_resident_blocks(int d, size_t lds_bytes);
+// the iteration options); false if the problem needs a single block (unless
+// allow_single), more than kMeshMaxBlocks blocks, or more than lds_cap bytes of
+// LDS per block.  Returns the grid size in *blocks.
+bool mesh_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, bool allow_single,
+               MeshArgs& A, size_t& lds_bytes, int* blocks);
+// Blocks of the exchange kernel (single problem, or the batch kernel) that fit
+// on the device at once with this much dynamic LDS each.
+int mesh_resident_blocks(int d, size_t lds_bytes, bool batch);
 hipError_t launch_mesh(int d, const MeshArgs& A, size_t lds_bytes, int blocks, hipStream_t s);
+// All problems of a batch in one launch: tab[p] (device) holds problem p's
+// arguments, blk_end[p] (device) the end of its blocks; lds_bytes is the largest
+// problem's dynamic LDS.
+hipError_t launch_mesh_batch(int d, const MeshArgs* tab, const int* blk_end, int nprob,
+                             size_t lds_bytes, int blocks, double pairs, hipStream_t s);
 
 // Per-launch event timing (ct_profile_enable); no-ops when disabled.
 bool profiling();

@@ -99,16 +99,18 @@ __device__ __forceinline__ void publish(unsigned long long* xch, int n, int row,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
+extern __shared__ float4 mesh_lds4[];
+
+// Block b of one problem's exchange solve.
 template <int D>
-__global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs A) {
-    extern __shared__ float4 lds4[];
+__device__ __forceinline__ void mesh_solve(const MeshArgs& A, const int b) {
+    float4* lds4 = mesh_lds4;
     float* lds = reinterpret_cast<float*>(lds4);
     const int tid = (int)threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const float ninf = -__builtin_huge_valf();
     const float kap = A.kappa;
-    const int b = (int)blockIdx.x;
     const int x0 = min(A.T, b * A.xr), x1 = min(A.T, x0 + A.xr);
     const int y0 = min(A.M, b * A.yr), y1 = min(A.M, y0 + A.yr);
 
@@ -253,15 +255,44 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs A) {
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(kMeshThreads) void k_mesh(MeshArgs A) {
+    mesh_solve<D>(A, (int)blockIdx.x);
+}
+
+// Many problems in one launch: blk_end[p] is the end of problem p's blocks.  A
+// block finds its problem, copies the problem's arguments into LDS and runs that
+// problem's exchange solve as its block (blockIdx.x - start).  Every problem
+// exchanges only among its own blocks.
+template <int D>
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_batch(const MeshArgs* __restrict__ tab,
+                                                             const int* __restrict__ blk_end,
+                                                             int nprob) {
+    __shared__ MeshArgs sA;
+    const int bid = (int)blockIdx.x;
+    int lo = 0, hi = nprob - 1;   // first problem whose blocks end after bid
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (blk_end[mid] > bid) hi = mid;
+        else lo = mid + 1;
+    }
+    const int start = lo ? blk_end[lo - 1] : 0;
+    const unsigned* src = reinterpret_cast<const unsigned*>(tab + lo);
+    unsigned* dst = reinterpret_cast<unsigned*>(&sA);
+    for (int i = (int)threadIdx.x; i < (int)(sizeof(MeshArgs) / 4); i += kMeshThreads) dst[i] = src[i];
+    __syncthreads();
+    mesh_solve<D>(sA, bid - start);
+}
+
 }  // namespace
 
-bool mesh_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, MeshArgs& A,
-               size_t& lds_bytes, int* blocks) {
+bool mesh_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, bool allow_single,
+               MeshArgs& A, size_t& lds_bytes, int* blocks) {
     std::memset(&A, 0, sizeof(A));
     lds_bytes = 0;
     *blocks = 0;
     const int G = std::max((T + kMeshRows - 1) / kMeshRows, (M + kMeshRows - 1) / kMeshRows);
-    if (G < 2 || G > kMeshMaxBlocks) return false;
+    if (G < (allow_single ? 1 : 2) || G > kMeshMaxBlocks) return false;
     // the words one thread gathers in a half-iteration
     const int gmax = std::max(M + (debias ? T : 0), T + (ref_iter ? M : 0));
     if (gmax > kMeshGatherPerThread * kMeshThreads) return false;
@@ -371,21 +402,41 @@ bool mesh_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, 
     return true;
 }
 
-int mesh_resident_blocks(int d, size_t lds_bytes) {
+hipError_t ensure_dynamic_lds(const void* fn, size_t bytes) {
+    if (bytes <= (size_t(64) << 10)) return hipSuccess;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void*>, size_t> set;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t& cur = set[std::make_pair(dev, fn)];
+    if (bytes <= cur) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) cur = bytes;
+    return e;
+}
+
+static const void* mesh_kernel(int d, bool batch) {
+    if (batch)
+        return d == 2 ? reinterpret_cast<const void*>(&k_mesh_batch<2>)
+                      : reinterpret_cast<const void*>(&k_mesh_batch<3>);
+    return d == 2 ? reinterpret_cast<const void*>(&k_mesh<2>)
+                  : reinterpret_cast<const void*>(&k_mesh<3>);
+}
+
+int mesh_resident_blocks(int d, size_t lds_bytes, bool batch) {
     static std::mutex mu;
     static std::map<std::pair<int, std::pair<int, size_t>>, int> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
-    const auto key = std::make_pair(dev, std::make_pair(d, lds_bytes));
+    const auto key = std::make_pair(dev * 2 + (batch ? 1 : 0), std::make_pair(d, lds_bytes));
     std::lock_guard<std::mutex> lk(mu);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     int per_cu = 0, cus = 0;
-    const void* fn = d == 2 ? reinterpret_cast<const void*>(&k_mesh<2>)
-                            : reinterpret_cast<const void*>(&k_mesh<3>);
-    if (lds_bytes > (size_t(64) << 10) &&
-        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
-            hipSuccess)
+    const void* fn = mesh_kernel(d, batch);
+    if (ensure_dynamic_lds(fn, lds_bytes) != hipSuccess)
         per_cu = 0;
     else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kMeshThreads, lds_bytes) !=
              hipSuccess)
@@ -401,11 +452,8 @@ hipError_t launch_mesh(int d, const MeshArgs& A, size_t lds_bytes, int blocks, h
     void* tok = profile_kernel_begin(&e0, &e1);
     const double pairs = (double)A.iters * ((double)A.T * A.M * 2 + (A.debias ? (double)A.T * A.T : 0.0) +
                                             (A.ref_iter ? (double)A.M * A.M : 0.0));
-    const void* fn = d == 2 ? reinterpret_cast<const void*>(&k_mesh<2>)
-                            : reinterpret_cast<const void*>(&k_mesh<3>);
-    if (lds_bytes > (size_t(64) << 10)) {
-        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)lds_bytes);
+    {
+        const hipError_t e = ensure_dynamic_lds(mesh_kernel(d, false), lds_bytes);
         if (e != hipSuccess) return e;
     }
     if (d == 2) {
@@ -418,6 +466,28 @@ hipError_t launch_mesh(int d, const MeshArgs& A, size_t lds_bytes, int blocks, h
     const hipError_t e = hipGetLastError();
     // kind 40/41: a multi-workgroup exchange solve (safe / lagged from its first iteration)
     profile_kernel_end(tok, 40 + A.lagged0, 0, 0, blocks, pairs);
+    return e;
+}
+
+hipError_t launch_mesh_batch(int d, const MeshArgs* tab, const int* blk_end, int nprob,
+                             size_t lds_bytes, int blocks, double pairs, hipStream_t s) {
+    hipEvent_t e0, e1;
+    void* tok = profile_kernel_begin(&e0, &e1);
+    {
+        // set when the batch was planned (so not during a graph capture of the run)
+        const hipError_t e = ensure_dynamic_lds(mesh_kernel(d, true), lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    if (d == 2) {
+        if (e0) hipExtLaunchKernelGGL((k_mesh_batch<2>), dim3(blocks), dim3(kMeshThreads), lds_bytes, s, e0, e1, 0, tab, blk_end, nprob);
+        else hipLaunchKernelGGL((k_mesh_batch<2>), dim3(blocks), dim3(kMeshThreads), lds_bytes, s, tab, blk_end, nprob);
+    } else {
+        if (e0) hipExtLaunchKernelGGL((k_mesh_batch<3>), dim3(blocks), dim3(kMeshThreads), lds_bytes, s, e0, e1, 0, tab, blk_end, nprob);
+        else hipLaunchKernelGGL((k_mesh_batch<3>), dim3(blocks), dim3(kMeshThreads), lds_bytes, s, tab, blk_end, nprob);
+    }
+    const hipError_t e = hipGetLastError();
+    // kind 42: the exchange solve of a whole batch in one launch
+    profile_kernel_end(tok, 42, 0, 0, blocks, pairs);
     return e;
 }
 

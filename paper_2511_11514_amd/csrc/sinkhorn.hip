@@ -669,8 +669,8 @@ static ct_status run_mesh(const SkLayout& L, const SkConsts& c, const ct_sinkhor
     size_t lds = 0;
     int blocks = 0;
     const size_t cap = std::min(kTinyMaxLds, device_max_lds());
-    const bool planned = mesh_plan(T, M, d, debias, ref_iter, cap, A, lds, &blocks);
-    if (!planned || blocks > mesh_resident_blocks(d, lds)) {
+    const bool planned = mesh_plan(T, M, d, debias, ref_iter, cap, false, A, lds, &blocks);
+    if (!planned || blocks > mesh_resident_blocks(d, lds, false)) {
         if (forced)
             return fail(CT_E_UNSUPPORTED, "the exchange solve has no plan for T=%d, M=%d (it needs "
                                           "2 to %d blocks of at most %d rows and every point in "

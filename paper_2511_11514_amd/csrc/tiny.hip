@@ -345,10 +345,8 @@ bool tiny_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, 
 template <int D, int R>
 static hipError_t launch_tiny_dr(const TinyArgs& A, size_t lds_bytes, hipStream_t s,
                                  hipEvent_t e0, hipEvent_t e1) {
-    if (lds_bytes > (size_t(64) << 10)) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tiny<D, R>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes);
+    {
+        const hipError_t e = ensure_dynamic_lds(reinterpret_cast<const void*>(&k_tiny<D, R>), lds_bytes);
         if (e != hipSuccess) return e;
     }
     if (e0)
