@@ -113,7 +113,7 @@ const char* ct_version(void);
                            fit in one workgroup's LDS).  Without any of CT_FUSED,
                            CT_UNFUSED, CT_TINY and CT_MESH (at most one may be given) the
                            library picks, by the point pairs of one iteration: the
-                           one-workgroup solve up to 4e4, the exchange solve up to 2e7 where
+                           one-workgroup solve up to 4e4, the exchange solve up to 1.5e7 where
                            it plans, else the one-workgroup solve up to 1.5e5, the fused
                            solve up to 1.05e6, and per-sweep launches beyond. */
 #define CT_DIFFERENCE 1024u /* per-sweep launches: evaluate the lagged sweeps' exponent in the
@@ -244,7 +244,7 @@ ct_status ct_status_sync(const void* ws, float resid_tol, uint32_t* nonfinite, u
  *     batch, each problem given the blocks of its exchange solve (see CT_MESH:
  *     every point of the problem in each block's LDS, at most 64 own rows of x and
  *     of y per block, potentials passed between the problem's blocks as versioned
- *     words); it applies when every problem has at most 2e7 point pairs per
+ *     words); it applies when every problem has at most 1.5e7 point pairs per
  *     iteration and fits one workgroup's LDS and all the blocks fit on the device
  *     at once (decided by ct_sinkhorn_batched_prepare; CT_E_UNSUPPORTED there for
  *     CT_MESH when it does not apply);

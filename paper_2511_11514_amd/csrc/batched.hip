@@ -735,7 +735,7 @@ size_t build_lock(const BLayout& L, const std::vector<BProb>& P, uint32_t flags,
 // at most kMeshBatchPairs point pairs per iteration each, all blocks resident at
 // once.  Fills tab/blk (device pointers of L) and returns false if it does not
 // apply.
-constexpr double kMeshBatchPairs = 2.0e7;
+constexpr double kMeshBatchPairs = 1.5e7;
 constexpr unsigned kMeshBatchWaitPolls = 1u << 18;
 
 size_t device_lds_per_block() {

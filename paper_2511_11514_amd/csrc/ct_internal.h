@@ -224,15 +224,16 @@ constexpr int kMeshThreads = 1024;                 // 16 waves
 constexpr int kMeshWaves = kMeshThreads / 64;
 constexpr int kMeshRows = 64;                      // rows of one point set per block, at most
 constexpr int kMeshMaxBlocks = 64;
-constexpr int kMeshGatherPerThread = 4;            // words one thread gathers per half-iteration
+constexpr int kMeshGatherPerThread = 8;            // words one thread gathers per half-iteration
 // One soft-min job of a half-iteration over the block's own rows.  Offsets are
 // in float4 units for record arrays and in float units for everything else;
-// row-indexed arrays are indexed by the global row.
+// record arrays are indexed by the global row, potential arrays by the row's
+// place among the block's own rows.
 struct MeshJob {
     int yside;             // rows of y (g, q) rather than of x (f, p)
     int keys;              // key points
     int qrec, krec;        // record arrays of the rows / keys
-    int qnorm, qpot;       // |q'|^2 and the potential of the rows
+    int qpot;              // potential of the block's own rows (from its first own row)
     int avg;               // 1: new = (old + T)/2 (self problems)
     int splits, kps;       // key ranges, keys per range
     int task0;             // first task index of the job within its half-iteration
@@ -243,8 +244,7 @@ struct MeshJob {
 struct MeshGather {
     const unsigned long long* xch;   // [2][n]
     int n;                 // points
-    int rec;               // record array that takes H = h - |v'|^2
-    int norm;              // |v'|^2
+    int rec;               // record array that takes H = h - |v'|^2 (|v'|^2 from its (2v'))
     int lw;                // log2 mass, or -1: the constant log2a
     int lag;               // 0: the version the iteration starts from, 1: the next one
 };
@@ -271,7 +271,7 @@ struct MeshArgs {
     int ngat[2];
     // LDS offsets: record arrays (float4 units), then floats
     int o_rf, o_rg, o_rp, o_rq;
-    int o_f, o_g, o_p, o_q, o_lb, o_nx, o_ny, o_ps, o_pm;
+    int o_f, o_g, o_p, o_q, o_lb, o_ps, o_pm;
     int ntask_max;
     double est_cycles;     // the plan's modelled cycles per iteration (compute only)
 };

@@ -47,6 +47,12 @@ __device__ __forceinline__ unsigned long long ldx(const unsigned long long* w) {
     return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// |v'|^2 from a record's (2v'): a power-of-two scaling of the same FMA chain, so
+// the same float as when formed from v' itself.
+__device__ __forceinline__ float rec_norm(float x2, float y2, float z2) {
+    return 0.25f * __builtin_fmaf(x2, x2, __builtin_fmaf(y2, y2, z2 * z2));
+}
+
 // Gather the half-iteration's potentials into the key records.  A thread takes
 // up to kMeshGatherPerThread words: their first loads are issued together, then
 // each word not yet at the awaited version is polled on its own.
@@ -87,8 +93,8 @@ __device__ __forceinline__ void gather(const MeshArgs& A, int h, int k, float* l
         const float v = __uint_as_float((unsigned)w[s]);
         const int lw = sec ? G1.lw : G0.lw;
         const float l = lw >= 0 ? lds[lw + i] : A.log2a;
-        lds[4 * ((sec ? G1.rec : G0.rec) + i) + 3] =
-            __builtin_fmaf(v, A.kappa, l) - lds[(sec ? G1.norm : G0.norm) + i];
+        float* rec = lds + 4 * ((sec ? G1.rec : G0.rec) + i);
+        rec[3] = __builtin_fmaf(v, A.kappa, l) - rec_norm(rec[0], rec[1], rec[2]);
     }
 }
 
@@ -114,38 +120,37 @@ __device__ __forceinline__ void mesh_solve(const MeshArgs& A, const int b) {
     const int x0 = min(A.T, b * A.xr), x1 = min(A.T, x0 + A.xr);
     const int y0 = min(A.M, b * A.yr), y1 = min(A.M, y0 + A.yr);
 
-    // load: every point's record (2v', .w filled by the gathers), norms, log2 b;
-    // the own rows' potentials, published as version 0
+    // load: every point's record (2v', .w filled by the gathers) and log2 b; the
+    // own rows' potentials (indexed from the block's first own row), published as
+    // version 0
     for (int i = tid; i < A.T; i += kMeshThreads) {
         const float4 c = A.cx[i];
         const float4 r = make_float4(2.f * c.x, 2.f * c.y, D == 3 ? 2.f * c.z : 0.f, 0.f);
         lds4[A.o_rf + i] = r;
         if (A.debias) lds4[A.o_rp + i] = r;
-        lds[A.o_nx + i] = norm2<D>(c);
     }
     for (int j = tid; j < A.M; j += kMeshThreads) {
         const float4 c = A.cy[j];
         const float4 r = make_float4(2.f * c.x, 2.f * c.y, D == 3 ? 2.f * c.z : 0.f, 0.f);
         lds4[A.o_rg + j] = r;
         if (A.ref_iter) lds4[A.o_rq + j] = r;
-        lds[A.o_ny + j] = norm2<D>(c);
         lds[A.o_lb + j] = A.log2b[j];
     }
     for (int i = x0 + tid; i < x1; i += kMeshThreads) {
-        lds[A.o_f + i] = A.f[i];   // f's version 0 is never awaited: iteration 0 reads version 1
+        lds[A.o_f + i - x0] = A.f[i];   // f's version 0 is never awaited: iteration 0 reads version 1
         if (A.debias) {
             const float p = A.p[i];
-            lds[A.o_p + i] = p;
+            lds[A.o_p + i - x0] = p;
             publish(A.xch_p, A.T, i, 0u, p);
         }
     }
     for (int j = y0 + tid; j < y1; j += kMeshThreads) {
         const float g = A.g[j];
-        lds[A.o_g + j] = g;
+        lds[A.o_g + j - y0] = g;
         publish(A.xch_g, A.M, j, 0u, g);
         if (A.ref_iter) {
             const float q = A.q[j];
-            lds[A.o_q + j] = q;
+            lds[A.o_q + j - y0] = q;
             publish(A.xch_q, A.M, j, 0u, q);
         }
     }
@@ -167,11 +172,11 @@ __device__ __forceinline__ void mesh_solve(const MeshArgs& A, const int b) {
                 const int split = t - J.task0;
                 const int k0 = min(J.keys, split * J.kps), k1 = min(J.keys, k0 + J.kps);
                 // lanes past the last row repeat it; the combine never reads them
-                const int row = r0 + min(lane, nr - 1);
-                const float4 v = lds4[J.qrec + row];
+                const int lr = min(lane, nr - 1);
+                const float4 v = lds4[J.qrec + r0 + lr];
                 const float q[1][3] = {{0.5f * v.x, 0.5f * v.y, 0.5f * v.z}};
-                float m[1] = {lagged ? -lds[J.qpot + row] * kap : 0.f};
-                const float C[1] = {-lds[J.qnorm + row] - m[0]};
+                float m[1] = {lagged ? -lds[J.qpot + lr] * kap : 0.f};
+                const float C[1] = {-rec_norm(v.x, v.y, v.z) - m[0]};
                 float s[1];
                 if (lagged) sum_lagged<D, 1>(lds4 + J.krec, k0, k1, q, C, s);
                 else sum_safe<D, 1>(lds4 + J.krec, k0, k1, q, C, m, s);
@@ -193,11 +198,10 @@ __device__ __forceinline__ void mesh_solve(const MeshArgs& A, const int b) {
                 const int task0 = sec ? J1.task0 : J0.task0;
                 const int splits = sec ? J1.splits : J0.splits;
                 const int qpot = sec ? J1.qpot : J0.qpot;
-                const int qnorm = sec ? J1.qnorm : J0.qnorm;
                 const int avg = sec ? J1.avg : J0.avg;
                 const float* ps = lds + A.o_ps + task0 * 64 + lrow;
                 const float* pm = lds + A.o_pm + task0 * 64 + lrow;
-                const float old = lds[qpot + row];
+                const float old = lds[qpot + lrow];
                 float mm, ss = 0.f;
                 if (lagged) {
                     mm = -old * kap;
@@ -214,7 +218,7 @@ __device__ __forceinline__ void mesh_solve(const MeshArgs& A, const int b) {
                     // the row's shift was unusable: recompute with a tracked maximum
                     const float4 v = lds4[(sec ? J1.qrec : J0.qrec) + row];
                     const float qv[1][3] = {{0.5f * v.x, 0.5f * v.y, 0.5f * v.z}};
-                    const float C1[1] = {-lds[qnorm + row]};
+                    const float C1[1] = {-rec_norm(v.x, v.y, v.z)};
                     float m1[1], s1[1];
                     sum_safe<D, 1>(lds4 + (sec ? J1.krec : J0.krec), 0, sec ? J1.keys : J0.keys,
                                    qv, C1, m1, s1);
@@ -224,7 +228,7 @@ __device__ __forceinline__ void mesh_solve(const MeshArgs& A, const int b) {
                 }
                 const float tn = -(mm + __log2f(ss)) * A.inv_kappa;
                 const float nv = avg ? 0.5f * (old + tn) : tn;
-                lds[qpot + row] = nv;
+                lds[qpot + lrow] = nv;
                 publish(sec ? J1.xch : J0.xch, (sec ? J1.yside : J0.yside) ? A.M : A.T, row,
                         (unsigned)(k + 1), nv);
             }
@@ -234,21 +238,21 @@ __device__ __forceinline__ void mesh_solve(const MeshArgs& A, const int b) {
     // store the own rows: potentials and the key terms the final pass reads
     const int hofs = D == 2 ? 2 : 3;
     for (int i = x0 + tid; i < x1; i += kMeshThreads) {
-        const float f = lds[A.o_f + i];
+        const float f = lds[A.o_f + i - x0];
         A.f[i] = f;
         reinterpret_cast<float*>(A.xrec_f + i)[hofs] = __builtin_fmaf(f, kap, A.log2a);
         if (A.debias) {
-            const float p = lds[A.o_p + i];
+            const float p = lds[A.o_p + i - x0];
             A.p[i] = p;
             reinterpret_cast<float*>(A.xrec_p + i)[hofs] = __builtin_fmaf(p, kap, A.log2a);
         }
     }
     for (int j = y0 + tid; j < y1; j += kMeshThreads) {
-        const float g = lds[A.o_g + j], lb = lds[A.o_lb + j];
+        const float g = lds[A.o_g + j - y0], lb = lds[A.o_lb + j];
         A.g[j] = g;
         reinterpret_cast<float*>(A.yrec_g + j)[hofs] = __builtin_fmaf(g, kap, lb);
         if (A.ref_iter) {
-            const float q = lds[A.o_q + j];
+            const float q = lds[A.o_q + j - y0];
             A.q[j] = q;
             reinterpret_cast<float*>(A.yrec_q + j)[hofs] = __builtin_fmaf(q, kap, lb);
         }
@@ -313,37 +317,35 @@ bool mesh_plan(int T, int M, int d, bool debias, bool ref_iter, size_t lds_cap, 
         off += n;
         return o;
     };
-    A.o_f = take(T);
-    A.o_g = take(M);
-    A.o_p = take(debias ? T : 0);
-    A.o_q = take(ref_iter ? M : 0);
+    // own rows only
+    A.o_f = take(A.xr);
+    A.o_g = take(A.yr);
+    A.o_p = take(debias ? A.xr : 0);
+    A.o_q = take(ref_iter ? A.yr : 0);
     A.o_lb = take(M);
-    A.o_nx = take(T);
-    A.o_ny = take(M);
-    auto mk = [&](int yside, int keys, int qrec, int krec, int qnorm, int qpot, int avg) {
+    auto mk = [&](int yside, int keys, int qrec, int krec, int qpot, int avg) {
         MeshJob j;
         std::memset(&j, 0, sizeof(j));
-        j.yside = yside; j.keys = keys; j.qrec = qrec; j.krec = krec; j.qnorm = qnorm;
-        j.qpot = qpot; j.avg = avg;
+        j.yside = yside; j.keys = keys; j.qrec = qrec; j.krec = krec; j.qpot = qpot; j.avg = avg;
         return j;
     };
     A.njobs[0] = A.njobs[1] = 0;
-    A.job[0][A.njobs[0]++] = mk(0, M, A.o_rf, A.o_rg, A.o_nx, A.o_f, 0);
-    if (debias) A.job[0][A.njobs[0]++] = mk(0, T, A.o_rf, A.o_rp, A.o_nx, A.o_p, 1);
-    A.job[1][A.njobs[1]++] = mk(1, T, A.o_rg, A.o_rf, A.o_ny, A.o_g, 0);
-    if (ref_iter) A.job[1][A.njobs[1]++] = mk(1, M, A.o_rg, A.o_rq, A.o_ny, A.o_q, 1);
+    A.job[0][A.njobs[0]++] = mk(0, M, A.o_rf, A.o_rg, A.o_f, 0);
+    if (debias) A.job[0][A.njobs[0]++] = mk(0, T, A.o_rf, A.o_rp, A.o_p, 1);
+    A.job[1][A.njobs[1]++] = mk(1, T, A.o_rg, A.o_rf, A.o_g, 0);
+    if (ref_iter) A.job[1][A.njobs[1]++] = mk(1, M, A.o_rg, A.o_rq, A.o_q, 1);
     // gathers: half 0 needs g and p as the iteration starts; half 1 the new f and q
-    auto gt = [&](int n, int rec, int norm, int lw, int lag) {
+    auto gt = [&](int n, int rec, int lw, int lag) {
         MeshGather g;
         std::memset(&g, 0, sizeof(g));
-        g.n = n; g.rec = rec; g.norm = norm; g.lw = lw; g.lag = lag;
+        g.n = n; g.rec = rec; g.lw = lw; g.lag = lag;
         return g;
     };
     A.ngat[0] = A.ngat[1] = 0;
-    A.gat[0][A.ngat[0]++] = gt(M, A.o_rg, A.o_ny, A.o_lb, 0);
-    if (debias) A.gat[0][A.ngat[0]++] = gt(T, A.o_rp, A.o_nx, -1, 0);
-    A.gat[1][A.ngat[1]++] = gt(T, A.o_rf, A.o_nx, -1, 1);
-    if (ref_iter) A.gat[1][A.ngat[1]++] = gt(M, A.o_rq, A.o_ny, A.o_lb, 0);
+    A.gat[0][A.ngat[0]++] = gt(M, A.o_rg, A.o_lb, 0);
+    if (debias) A.gat[0][A.ngat[0]++] = gt(T, A.o_rp, -1, 0);
+    A.gat[1][A.ngat[1]++] = gt(T, A.o_rf, -1, 1);
+    if (ref_iter) A.gat[1][A.ngat[1]++] = gt(M, A.o_rq, A.o_lb, 0);
 
     // Key ranges: each job gets a share of the 16 waves' tasks in proportion to
     // its keys (at least 16 keys per range); a few multiples of 16 tasks are

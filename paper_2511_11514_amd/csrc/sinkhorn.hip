@@ -650,10 +650,11 @@ static ct_status run_tiny(const SkLayout& L, const SkConsts& c, const ct_sinkhor
 // cached reference potential, whole call (exchange / one-workgroup / fused /
 // per-sweep launches): T = 100: 0.63 / 0.59 / 1.34 / 1.41 ms; 300: 0.87 / 1.94 /
 // 1.87 / 2.26; 500: 1.08 / 3.65 / 2.63 / 2.66; 1000: 1.54 / - / 7.0 / 2.70;
-// 2000: 2.57 / - / 23.5 / 3.13.  CT_MESH forces it (CT_E_UNSUPPORTED when it
+// 2000: 2.57 / - / 23.5 / 3.13; 2500 (1.9e7 pairs): 3.20 against 3.16 for per-sweep
+// launches, so the default stops below.  CT_MESH forces it (CT_E_UNSUPPORTED when it
 // cannot plan); CT_FUSED, CT_UNFUSED and CT_TINY rule it out.
 constexpr double kMeshMinPairs = 40000.0;
-constexpr double kMeshAutoPairs = 2.0e7;
+constexpr double kMeshAutoPairs = 1.5e7;
 constexpr unsigned kMeshWaitPolls = 1u << 18;
 
 static ct_status run_mesh(const SkLayout& L, const SkConsts& c, const ct_sinkhorn_opts* o,

@@ -111,6 +111,29 @@ def test_mesh_cached_reference_and_planner(ct):
     assert rel(u1 - u0, r_u1 - u0) < TOL
 
 
+def test_mesh_at_the_longest_sinkhorn_horizon(ct):
+    """T = M = 2500 in 3-D (the longest horizon of the paper's Sinkhorn sweep), the
+    reference self potential cached as the planner does: 40 workgroups, each with
+    every point in LDS; against the per-sweep launches with the same cached
+    potential, and the uncached 2-D case T = 1200, M = 2000 against the oracle."""
+    dev = torch.device("cuda")
+    cfg = W.CONFIGS["autograd_3d"]
+    x, y, w, _g = W.config_inputs(cfg, T=2500, M=2500)
+    q = ct.reference_self_potential(torch.as_tensor(y, device=dev), torch.as_tensor(w, device=dev),
+                                    eps=0.01, iters=30)
+    print("exchange T=M=2500 d=3 cached reference potential", flush=True)
+    a = _run(ct, x, y, w, 0.01, 30, fused="mesh", ref_q=q.cpu().numpy())
+    b = _run(ct, x, y, w, 0.01, 30, fused=False, ref_q=q.cpu().numpy())
+    for k in ("grad_x", "grad_w"):
+        assert rel(a[k], b[k]) < 2e-6, (k, rel(a[k], b[k]))
+    cfg = W.CONFIGS["grad_2d"]
+    x, y, w, _g = W.config_inputs(cfg, T=1200, M=2000)
+    g = _run(ct, x, y, w, 0.01, 25, fused="mesh")
+    r = oracle.sinkhorn(x, y, w, eps=0.01, iters=25)
+    e = _errs(g, r, 1200, 2000, w)
+    assert max(e.values()) < TOL, e
+
+
 def test_mesh_rejects_problems_it_cannot_plan(ct):
     # one block's worth of rows: the one-workgroup solve's case
     x, y, w, _g = W.config_inputs(W.CONFIGS["grad_2d"], T=40, M=64)
