@@ -87,7 +87,11 @@ def test_cached_reference_potential_matches_recomputing_it(ct):
     """The reference self potential does not depend on the trajectory (eq. 6's
     OT(b, b)): computed once (reference_self_potential) and passed as ref_q, the
     value and both gradients match a call that iterates it, within float32
-    rounding, and the FP64 oracle at 1e-5."""
+    rounding, and the FP64 oracle at 1e-5.  With one launch per sweep the key
+    ranges of the cross sweeps do not depend on whether q is iterated, so dS/dx is
+    bit-equal; the exchange solve (the automatic choice at this size) shares its
+    waves between the g and q rows, so g is summed in another order when q is
+    cached and dS/dx agrees to float32 rounding."""
     dev = torch.device("cuda")
     x, y, _w, _g = W.config_inputs(W.CONFIGS["roofline_2d"], T=1200, M=3001)
     w = np.random.default_rng(7).uniform(0.5, 1.5, len(y)).astype(np.float32)
@@ -103,7 +107,10 @@ def test_cached_reference_potential_matches_recomputing_it(ct):
     torch.cuda.synchronize()
     r = oracle.sinkhorn(x, y, w, eps=eps, iters=K)
     assert rel(q.cpu().numpy(), r.q) < 1e-6
-    assert torch.equal(cached.grad_x, full.grad_x)          # q does not enter dS/dx
+    assert rel(cached.grad_x.cpu().numpy(), full.grad_x.cpu().numpy()) < 2e-6
+    a = ct.sinkhorn_grad(xt, yt, wt, eps=eps, iters=K, fused=False)
+    b = ct.sinkhorn_grad(xt, yt, wt, eps=eps, iters=K, ref_q=q, fused=False)
+    assert torch.equal(a.grad_x, b.grad_x)                  # q does not enter dS/dx
     assert rel(cached.grad_w.cpu().numpy(), full.grad_w.cpu().numpy()) < 1e-6
     assert abs(cached.value.item() - full.value.item()) <= 1e-6 * abs(full.value.item())
     assert torch.equal(xr.grad, cached.grad_x) and torch.equal(wr.grad, cached.grad_w)
