@@ -110,6 +110,7 @@ struct MedState {
     int mode;                    // 0: select over all pairs, 1: over the bracket's candidates
     unsigned long long below;    // pairs below the bracket
     unsigned long long ncand;    // pairs inside the bracket (may exceed the buffer)
+    unsigned nitems;             // pairs of groups listed for the pair-by-pair pass
 };
 
 // Large T: an exact selection over a bracket.  kMedSample pseudo-random pairs
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(256) void k_med_init(MedState* st, unsigned long lo
         st->mode = 0;
         st->below = 0ull;
         st->ncand = 0ull;
+        st->nitems = 0u;
     }
 }
 
@@ -301,122 +303,426 @@ __global__ __launch_bounds__(256) void k_flat_hist(const float* __restrict__ v, 
     }
 }
 
-// One pass over all pairs i < j (tiled as k_med_hist): count the pairs below the
-// bracket [lo, hi] found on the sample and collect those inside.  Each thread
-// keeps up to kCandSlots candidates of a tile in its own LDS column (plain
-// stores, no atomics in the pair loop); after the tile a block prefix sum of
-// the counts places them in the global buffer with one append per block.  A
-// thread with more than kCandSlots in one tile appends the rest directly.
-constexpr int kCandSlots = 16;
-constexpr int kBracketRows = 4;                  // rows per thread: tiles of 1024 x 256
+// One pass over all pairs i < j: count the pairs below the bracket [lo, hi]
+// found on the sample and collect those inside.  The pass runs over the points
+// in a spatial order (cells of a Morton curve), in groups of kBoxPts consecutive
+// points with a bounding box each, so that most pairs of groups are settled by
+// their boxes alone: a pair of groups whose largest squared distance is below lo
+// adds all of its pairs to the count, one whose smallest is above hi adds
+// nothing, and only the rest are evaluated pair by pair.  The boxes' squared
+// distances take the same rounded operations as a pair's (sqdist), and rounding
+// is monotonic, so they bound every pair's float32 value exactly; a box with a
+// non-finite coordinate is NaN and its groups are always evaluated.  The
+// unordered pairs {i, j} and their values are those of the original order.
+constexpr int kBoxPts = 64;                       // points per box: a wave's rows, a quarter tile's columns
+constexpr int kWaveBuf = 960;                    // candidates a wave holds in LDS (8 blocks per CU)
+constexpr int kCells2 = 1 << 15;                 // cell counts: 128 x 128 cells (2-D), 32 x 32 x 32 (3-D)
 
-inline int bracket_grid(int T) {
-    const int ntr = (T + 256 * kBracketRows - 1) / (256 * kBracketRows), ntc = (T + 255) / 256;
-    return std::min(ntr * ntc, kNumCU * 8);
+
+
+__global__ __launch_bounds__(256) void k_fill_u32(unsigned* __restrict__ p, int n, unsigned v) {
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
-// The pairs of one bracket tile: count those below the bracket, keep those in it
-// (the first kCandSlots per thread in LDS slots, the rest straight to the global
-// candidate list).  CHECK keeps only pairs with j > i (diagonal and ragged tiles).
-template <int D, int RB, bool CHECK>
-__device__ __forceinline__ void bracket_pairs(const float4* cj, int n, int j0, const float4 (&xi)[RB],
-                                              const int (&ir)[RB], unsigned lo, unsigned span,
-                                              unsigned& bl, unsigned& nin,
-                                              float (*slots)[256], MedState* st,
-                                              float* __restrict__ cand, unsigned long long cap) {
-    for (int jj = 0; jj < n; jj += 8) {
+// Bounding box of all points (one block): box[0] = min, box[1] = max.
+__global__ __launch_bounds__(1024) void k_med_box(const float4* __restrict__ c, int T,
+                                                  float4* __restrict__ box) {
+    __shared__ float red[6][16];
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll 8
+    for (int i = threadIdx.x; i < T; i += 1024) {
+        const float4 p = c[i];
+        v[0] = fminf(v[0], p.x); v[1] = fminf(v[1], p.y); v[2] = fminf(v[2], p.z);
+        v[3] = fmaxf(v[3], p.x); v[4] = fmaxf(v[4], p.y); v[5] = fmaxf(v[5], p.z);
+    }
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-            const int jl = jj + g;
-            if (jl < n) {
-                const float4 xj = cj[jl];
-                const int j = j0 + jl;
+    for (int k = 0; k < 6; ++k) {
+        for (int o = 32; o > 0; o >>= 1) {
+            const float u = __shfl_down(v[k], o, 64);
+            v[k] = k < 3 ? fminf(v[k], u) : fmaxf(v[k], u);
+        }
+        if (lane == 0) red[k][wave] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float m = red[k][0];
+        for (int w = 1; w < 16; ++w) m = k < 3 ? fminf(m, red[k][w]) : fmaxf(m, red[k][w]);
+        reinterpret_cast<float*>(box)[(k < 3 ? 0 : 4) + k % 3] = m;
+    }
+}
+
+__device__ __forceinline__ unsigned spread2(unsigned v) {    // 7 bits -> even bits of 14
+    v &= 0x7Fu;
+    v = (v | (v << 4)) & 0x070Fu;
+    v = (v | (v << 2)) & 0x3333u;
+    return (v | (v << 1)) & 0x5555u;
+}
+__device__ __forceinline__ unsigned spread3(unsigned v) {    // 5 bits -> every third bit of 15
+    v &= 0x1Fu;
+    v = (v | (v << 8)) & 0x100Fu;
+    v = (v | (v << 4)) & 0x10C3u;
+    return (v | (v << 2)) & 0x1249u;
+}
+
+// Cell of each point on the Morton curve over the bounding box, and the cell counts.
+template <int D>
+__global__ __launch_bounds__(256) void k_med_cell(const float4* __restrict__ c, int T,
+                                                  const float4* __restrict__ box,
+                                                  unsigned* __restrict__ cell,
+                                                  unsigned* __restrict__ count) {
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= T) return;
+    const float4 p = c[i], lo = box[0], hi = box[1];
+    constexpr float side = D == 2 ? 128.f : 32.f;
+    auto q = [&](float x, float a, float b) {
+        const float s = (x - a) / fmaxf(b - a, 1e-30f) * side;      // NaN: cell 0
+        return (unsigned)fminf(fmaxf(s, 0.f), side - 1.f);
+    };
+    const unsigned k = D == 2 ? spread2(q(p.x, lo.x, hi.x)) | (spread2(q(p.y, lo.y, hi.y)) << 1)
+                              : spread3(q(p.x, lo.x, hi.x)) | (spread3(q(p.y, lo.y, hi.y)) << 1) |
+                                    (spread3(q(p.z, lo.z, hi.z)) << 2);
+    cell[i] = k;
+    atomicAdd(&count[k], 1u);
+}
+
+// Exclusive prefix sum of the kCells2 cell counts, in place (one block).
+__global__ __launch_bounds__(1024) void k_med_cell_scan(unsigned* __restrict__ count) {
+    constexpr int per = kCells2 / 1024;
+    __shared__ unsigned wsum[16];
+    unsigned v[per];
+    unsigned loc = 0u;
+    const unsigned* src = count + threadIdx.x * per;
 #pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    const float d2 = sqdist<D>(xi[r], xj);
-                    const unsigned u = __float_as_uint(d2);
-                    const bool ok = !CHECK || j > ir[r];
-                    bl += (ok && u < lo) ? 1u : 0u;
-                    if (ok && u - lo <= span) {
-                        if (nin < (unsigned)kCandSlots) {
-                            slots[nin][threadIdx.x] = d2;
-                        } else {
-                            const unsigned long long gi = atomicAdd(&st->ncand, 1ull);
-                            if (gi < cap) cand[gi] = d2;
-                        }
-                        ++nin;
-                    }
-                }
-            }
+    for (int k = 0; k < per; ++k) {
+        v[k] = src[k];
+        loc += v[k];
+    }
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    unsigned inc = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    unsigned run = inc - loc;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        count[threadIdx.x * per + k] = run;
+        run += v[k];
+    }
+}
+
+// Points in cell order (the order inside a cell is immaterial).
+__global__ __launch_bounds__(256) void k_med_cell_scatter(const float4* __restrict__ c, int T,
+                                                          const unsigned* __restrict__ cell,
+                                                          unsigned* __restrict__ cursor,
+                                                          float4* __restrict__ cs) {
+    const int i = blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= T) return;
+    cs[atomicAdd(&cursor[cell[i]], 1u)] = c[i];
+}
+
+// Box of each group of kBoxPts consecutive points (a wave per group): gbox[2g]
+// = min, gbox[2g + 1] = max; NaN if a coordinate is not finite.
+__global__ __launch_bounds__(256) void k_med_group_box(const float4* __restrict__ cs, int T,
+                                                       float4* __restrict__ gbox) {
+    const int g = blockIdx.x * 4 + ((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+    const int ng = (T + kBoxPts - 1) / kBoxPts;
+    if (g >= ng) return;
+    const int i = g * kBoxPts + lane;
+    float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    if (i < T) {
+        const float4 p = cs[i];
+        v[0] = v[3] = p.x;
+        v[1] = v[4] = p.y;
+        v[2] = v[5] = p.z;
+        bad = !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z));
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+        for (int o = 32; o > 0; o >>= 1) {
+            const float u = __shfl_xor(v[k], o, 64);
+            v[k] = k < 3 ? fminf(v[k], u) : fmaxf(v[k], u);
+        }
+    bad = __any(bad);
+    if (lane == 0) {
+        const float n = __int_as_float(0x7FC00000);
+        gbox[2 * g] = bad ? make_float4(n, n, n, 0.f) : make_float4(v[0], v[1], v[2], 0.f);
+        gbox[2 * g + 1] = bad ? make_float4(n, n, n, 0.f) : make_float4(v[3], v[4], v[5], 0.f);
+    }
+}
+
+// 1: every pair of the two boxes is below lo; 2: every pair is above hi; 0: evaluate.
+template <int D>
+__device__ __forceinline__ int box_class(const float4& alo, const float4& ahi, const float4& blo,
+                                         const float4& bhi, float lof, float hif) {
+    const float fx = fmaxf(ahi.x - blo.x, bhi.x - alo.x), fy = fmaxf(ahi.y - blo.y, bhi.y - alo.y);
+    const float gx = fmaxf(fmaxf(alo.x - bhi.x, blo.x - ahi.x), 0.f);
+    const float gy = fmaxf(fmaxf(alo.y - bhi.y, blo.y - ahi.y), 0.f);
+    float cmax = fy * fy, cmin = gy * gy;
+    if (D == 3) {
+        const float fz = fmaxf(ahi.z - blo.z, bhi.z - alo.z);
+        const float gz = fmaxf(fmaxf(alo.z - bhi.z, blo.z - ahi.z), 0.f);
+        cmax = __builtin_fmaf(fz, fz, cmax);
+        cmin = __builtin_fmaf(gz, gz, cmin);
+    }
+    const float dmax = __builtin_fmaf(fx, fx, cmax), dmin = __builtin_fmaf(gx, gx, cmin);
+    // NaN boxes compare false both ways
+    if (dmax < lof) return 1;
+    if (dmin > hif) return 2;
+    return 0;
+}
+
+// Append the n candidates in buf (this wave's LDS buffer) to the global list,
+// one atomic for the wave.
+__device__ __forceinline__ void wave_append(const float* buf, unsigned n, MedState* st,
+                                            float* __restrict__ cand, unsigned long long cap,
+                                            int lane) {
+    // the lanes read what other lanes of the wave wrote
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned long long base = 0ull;
+    if (lane == 0) base = atomicAdd(&st->ncand, (unsigned long long)n);
+    base = __shfl(base, 0, 64);
+    for (unsigned k = (unsigned)lane; k < n; k += 64)
+        if (base + k < cap) cand[base + k] = buf[k];
+    // the buffer is refilled only after every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One pair per lane: count it if below the bracket; if inside, pack it densely
+// into the wave's LDS buffer (a lane's place: nbuf plus the lanes of the mask
+// below it).  bl counts per lane; nbuf is wave-uniform; ok = false drops the pair.
+__device__ __forceinline__ void bracket_pair(float d2, bool ok, unsigned lo, unsigned span,
+                                             unsigned& bl, unsigned& nbuf, float* buf) {
+    const unsigned u = __float_as_uint(d2);
+    bl += (ok && u < lo) ? 1u : 0u;
+    const bool in = ok && u - lo <= span;
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(in);
+    if (m) {
+        const unsigned pos = __builtin_amdgcn_mbcnt_hi(
+            (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, nbuf));
+        if (in) buf[pos] = d2;
+        nbuf += (unsigned)__popcll(m);
+    }
+}
+
+// One row per lane against the columns [c0, c1) of the staged columns cj
+// (column c is point j0 + c), appending the wave's buffer to the global list
+// when the next eight columns could overflow it.  CHECK keeps only pairs with
+// j > i.  c0 is a multiple of 64 and c1 <= c0 + 64, so reading eight columns
+// from any chunk start stays inside the 64 (a column past c1 is skipped).
+template <int D, bool CHECK>
+__device__ __forceinline__ void bracket_row(const float4* cj, int c0, int c1, int j0, const float4& xi,
+                                            int ir, unsigned lo, unsigned span, unsigned& bl,
+                                            unsigned& nbuf, float* buf, MedState* st,
+                                            float* __restrict__ cand, unsigned long long cap,
+                                            int lane) {
+    for (int jj = c0; jj < c1; jj += 8) {
+        if (nbuf > (unsigned)(kWaveBuf - 8 * 64)) {
+            wave_append(buf, nbuf, st, cand, cap, lane);
+            nbuf = 0u;
+        }
+        float4 xj[8];
+#pragma unroll
+        for (int g = 0; g < 8; ++g) xj[g] = cj[jj + g];
+        if (jj + 8 <= c1) {
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+                bracket_pair(sqdist<D>(xi, xj[g]), !CHECK || j0 + jj + g > ir, lo, span, bl, nbuf, buf);
+        } else {
+#pragma unroll
+            for (int g = 0; g < 8; ++g)
+                if (jj + g < c1)
+                    bracket_pair(sqdist<D>(xi, xj[g]), !CHECK || j0 + jj + g > ir, lo, span, bl, nbuf,
+                                 buf);
         }
     }
 }
 
+// The pairs of groups (gr <= gc) the boxes do not settle, listed as
+// gr | gc << 16, and the pairs the boxes put below the bracket.  Block (x, y):
+// gr = y against gc = 256 x + thread; block b = y * gridDim.x + x.  Pass 0
+// writes each block's count of listed pairs and of pairs below; pass 1 (after
+// k_med_list_scan has turned the counts into offsets) writes the list in block
+// order.  No atomics: the list and the counts are the same on every run.
 template <int D>
-__global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ c, int T,
+__global__ __launch_bounds__(256) void k_med_classify(const float4* __restrict__ gbox, int T,
+                                                      const MedState* __restrict__ sst, int pass,
+                                                      unsigned* __restrict__ counts,
+                                                      unsigned long long* __restrict__ belows,
+                                                      unsigned* __restrict__ list) {
+    __shared__ unsigned wsum[4];
+    __shared__ unsigned long long wbel[4];
+    const int ng = (T + kBoxPts - 1) / kBoxPts;
+    const int gr = blockIdx.y, gc = blockIdx.x * 256 + (int)threadIdx.x;
+    const int b = blockIdx.y * gridDim.x + blockIdx.x;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const float lof = __uint_as_float(sst->prefix[0]), hif = __uint_as_float(sst->prefix[1]);
+    bool keep = false;
+    unsigned long long bel = 0ull;
+    if (gc >= gr && gc < ng) {
+        if (gc == gr) {
+            keep = true;
+        } else {
+            const int c = box_class<D>(gbox[2 * gr], gbox[2 * gr + 1], gbox[2 * gc], gbox[2 * gc + 1],
+                                       lof, hif);
+            // gr < gc: all kBoxPts rows of gr exist
+            if (c == 1) bel = (unsigned long long)kBoxPts * (unsigned long long)min(kBoxPts, T - kBoxPts * gc);
+            keep = c == 0;
+        }
+    }
+    const unsigned long long m = __builtin_amdgcn_ballot_w64(keep);
+    const unsigned pos = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bel += __shfl_down(bel, o, 64);
+    if (lane == 0) {
+        wsum[wave] = (unsigned)__popcll(m);
+        wbel[wave] = bel;
+    }
+    __syncthreads();
+    unsigned before = 0u, total = 0u;
+    unsigned long long btot = 0ull;
+    for (int w = 0; w < 4; ++w) {
+        before += w < wave ? wsum[w] : 0u;
+        total += wsum[w];
+        btot += wbel[w];
+    }
+    if (pass == 0) {
+        if (threadIdx.x == 0) {
+            counts[b] = total;
+            belows[b] = btot;
+        }
+    } else if (keep) {
+        list[counts[b] + before + pos] = (unsigned)gr | ((unsigned)gc << 16);
+    }
+}
+
+// Exclusive prefix sum of the nb block counts (in place, one block), their
+// total as st->nitems, and the pairs below the bracket added to st->below.
+__global__ __launch_bounds__(1024) void k_med_list_scan(unsigned* __restrict__ counts,
+                                                        const unsigned long long* __restrict__ belows,
+                                                        int nb, MedState* st) {
+    __shared__ unsigned wsum[16];
+    __shared__ unsigned long long wbel[16];
+    const int per = (nb + 1023) / 1024;
+    const int k0 = (int)threadIdx.x * per, k1 = min(nb, k0 + per);
+    unsigned loc = 0u;
+    unsigned long long bel = 0ull;
+    for (int k = k0; k < k1; ++k) {
+        loc += counts[k];
+        bel += belows[k];
+    }
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    unsigned inc = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bel += __shfl_down(bel, o, 64);
+    if (lane == 63) wsum[wave] = inc;
+    if (lane == 0) wbel[wave] = bel;
+    __syncthreads();
+    unsigned run = inc - loc;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (int k = k0; k < k1; ++k) {
+        const unsigned c = counts[k];
+        counts[k] = run;
+        run += c;
+    }
+    if (threadIdx.x == 0) {
+        unsigned total = 0u;
+        unsigned long long btot = 0ull;
+        for (int w = 0; w < 16; ++w) {
+            total += wsum[w];
+            btot += wbel[w];
+        }
+        st->nitems = total;
+        st->below += btot;
+    }
+}
+
+// The listed pairs of groups, pair by pair: one pair of groups per wave at a
+// time (its 64 rows one per lane, its 64 columns staged in the wave's LDS), the
+// next pair's rows and columns read while this one is evaluated.  The list is
+// dealt to the waves in turn (every pair of groups costs about the same); a
+// wave reads its list entries 64 at a time, one per lane.
+template <int D>
+__global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ cs,
+                                                     const unsigned* __restrict__ list, int T,
                                                      const MedState* __restrict__ sst,
                                                      MedState* st, float* __restrict__ cand,
                                                      unsigned long long cap) {
-    constexpr int RB = kBracketRows;
-    __shared__ float4 cj[256];
-    __shared__ float slots[kCandSlots][256];
-    __shared__ unsigned wsum[4];
-    __shared__ unsigned long long base;
-    const int ntr = (T + 256 * RB - 1) / (256 * RB), ntc = (T + 255) / 256;
-    const int ntiles = ntr * ntc;
-    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    __shared__ float4 cjw[4][kBoxPts];
+    __shared__ float wbuf[4][kWaveBuf];
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    float* buf = wbuf[wave];
+    float4* cw = cjw[wave];
     const unsigned lo = sst->prefix[0], hi = sst->prefix[1];
     const unsigned span = hi - lo;                 // u in [lo, hi]  <=>  u - lo <= span
-    unsigned long long below = 0ull;
-    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        const int i0 = (t % ntr) * 256 * RB;
-        const int j0 = (t / ntr) * 256;
-        const int j1 = min(T, j0 + 256);
-        if (j1 - 1 <= i0) continue;               // no column j > any row i of the tile
-        __syncthreads();                           // previous tile: columns and slots consumed
-        if ((int)threadIdx.x < j1 - j0) cj[threadIdx.x] = c[j0 + threadIdx.x];
-        __syncthreads();
-        float4 xi[RB];
-        int ir[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            ir[r] = i0 + r * 256 + (int)threadIdx.x;
-            // rows past the end take j > T, which no column satisfies
-            xi[r] = ir[r] < T ? c[ir[r]] : make_float4(0.f, 0.f, 0.f, 0.f);
-            if (ir[r] >= T) ir[r] = T;
-        }
-        unsigned nin = 0u, bl = 0u;
-        const int n = j1 - j0;
-        // every row valid and below every column of the tile: no pair needs j > i
-        const bool off_diag = i0 + 256 * RB <= T && j0 >= i0 + 256 * RB;
-        if (off_diag)
-            bracket_pairs<D, RB, false>(cj, n, j0, xi, ir, lo, span, bl, nin, slots, st, cand, cap);
-        else
-            bracket_pairs<D, RB, true>(cj, n, j0, xi, ir, lo, span, bl, nin, slots, st, cand, cap);
-        below += bl;
-        // block exclusive prefix sum of the kept counts
-        const unsigned kept = min(nin, (unsigned)kCandSlots);
-        unsigned inc = kept;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned v = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += v;
-        }
-        if (lane == 63) wsum[wave] = inc;
-        __syncthreads();
-        unsigned before = 0u, total = 0u;
-        for (int w = 0; w < 4; ++w) {
-            before += w < wave ? wsum[w] : 0u;
-            total += wsum[w];
-        }
-        if (threadIdx.x == 0) base = total ? atomicAdd(&st->ncand, (unsigned long long)total) : 0ull;
-        __syncthreads();
-        const unsigned long long off = base + before + inc - kept;
-        for (unsigned k = 0; k < kept; ++k)
-            if (off + k < cap) cand[off + k] = slots[k][threadIdx.x];
+    const int n = (int)st->nitems;
+    const int nw = (int)gridDim.x * 4;
+    const int first = (int)blockIdx.x * 4 + wave;
+    // the wave's k-th pair of groups is list[first + k nw]; lane l holds entry
+    // k = 64 q + l of batch q
+    const int nmine = first < n ? (n - first + nw - 1) / nw : 0;
+    unsigned bl = 0u, nbuf = 0u;
+    unsigned batch = 0u;
+    if (lane < nmine) batch = list[first + lane * nw];
+    unsigned item = __shfl(batch, 0, 64);
+    float4 xr = make_float4(0.f, 0.f, 0.f, 0.f), xc = xr;
+    if (nmine > 0) {
+        xr = cs[min((int)(item & 0xFFFFu) * kBoxPts + lane, T - 1)];
+        xc = cs[min((int)(item >> 16) * kBoxPts + lane, T - 1)];
     }
+    for (int k = 0; k < nmine; ++k) {
+        const int gr = (int)(item & 0xFFFFu), gc = (int)(item >> 16);
+        const float4 xi = xr;
+        cw[lane] = xc;
+        // the lanes read the columns other lanes wrote
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (k + 1 < nmine) {
+            if (((k + 1) & 63) == 0) {
+                const int q = k + 1 + lane;
+                batch = q < nmine ? list[first + q * nw] : 0u;
+            }
+            item = __shfl(batch, (k + 1) & 63, 64);
+            xr = cs[min((int)(item & 0xFFFFu) * kBoxPts + lane, T - 1)];
+            xc = cs[min((int)(item >> 16) * kBoxPts + lane, T - 1)];
+        }
+        const int ncols = min(kBoxPts, T - kBoxPts * gc);
+        // rows past the end take j > T, which no column satisfies
+        const int ir = min(kBoxPts * gr + lane, T);
+        if (gr == gc)
+            bracket_row<D, true>(cw, 0, ncols, kBoxPts * gc, xi, ir, lo, span, bl, nbuf, buf, st, cand,
+                                 cap, lane);
+        else
+            bracket_row<D, false>(cw, 0, ncols, kBoxPts * gc, xi, ir, lo, span, bl, nbuf, buf, st,
+                                  cand, cap, lane);
+        // the columns are overwritten only after every lane has read them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (nbuf) wave_append(buf, nbuf, st, cand, cap, lane);
     // pairs below the bracket: a wave sum, then one atomic per wave
-    unsigned long long b = below;
+    unsigned long long b = bl;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) b += __shfl_down(b, o, 64);
     if (lane == 0 && b) atomicAdd(&st->below, b);
@@ -728,6 +1034,14 @@ struct SvLayout {
     unsigned long long* hist;
     float* score;
     float4* cmed;      // raw coordinates for the median
+    float4* box;       // [2] bounding box of the points (large T)
+    unsigned* cell;    // [T] Morton cell of each point (large T)
+    unsigned* ccount;  // [kCells2] cell counts, then their prefix sums (large T)
+    float4* cs;        // [T] the points in cell order (large T)
+    float4* gbox;      // [2 ceil(T / kBoxPts)] boxes of the groups of cs (large T)
+    unsigned* glist;   // [ng (ng + 1) / 2] pairs of groups left to evaluate (large T)
+    unsigned* gcount;  // [ng ceil(ng / 256)] per classifying block: listed pairs, then offsets
+    unsigned long long* gbelow;  // [same] per classifying block: pairs below the bracket
     float* origin;     // [4] mean of the samples, subtracted before the bandwidth scale
     float4* qc;
     float4* krec;
@@ -763,6 +1077,16 @@ static SvLayout sv_layout(void* ws, int T, int d) {
     L.cand = bracket ? a.take<float>((size_t)cand_cap(T)) : nullptr;
     L.score = a.take<float>((size_t)T * d);
     L.cmed = a.take<float4>(T);
+    L.box = bracket ? a.take<float4>(2) : nullptr;
+    L.cell = bracket ? a.take<unsigned>(T) : nullptr;
+    L.ccount = bracket ? a.take<unsigned>(kCells2) : nullptr;
+    L.cs = bracket ? a.take<float4>(T) : nullptr;
+    const size_t ngrp = (size_t)((T + kBoxPts - 1) / kBoxPts);
+    L.gbox = bracket ? a.take<float4>(2 * ngrp) : nullptr;
+    L.glist = bracket ? a.take<unsigned>(ngrp * (ngrp + 1) / 2) : nullptr;
+    const size_t nblk = ngrp * ((ngrp + 255) / 256);
+    L.gcount = bracket ? a.take<unsigned>(nblk) : nullptr;
+    L.gbelow = bracket ? a.take<unsigned long long>(nblk) : nullptr;
     L.origin = a.take<float>(4);
     L.qc = a.take<float4>(T);
     L.krec = a.take<float4>((size_t)Tpad * (d == 2 ? 1 : 2));
@@ -829,11 +1153,32 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
                 hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.sst, L.hist, pass, T, -1, 0);
                 CT_CHECK_HIP(hipGetLastError());
             }
-            const dim3 bgrid(bracket_grid(T));
+            // the points in Morton-cell order and the boxes of their groups
+            const int ng = (T + kBoxPts - 1) / kBoxPts;
+            hipLaunchKernelGGL(k_fill_u32, dim3(kCells2 / 256), dim3(256), 0, st, L.ccount, kCells2, 0u);
+            hipLaunchKernelGGL(k_med_box, dim3(1), dim3(1024), 0, st, L.cmed, T, L.box);
             if (d == 2)
-                hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
+                hipLaunchKernelGGL(k_med_cell<2>, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.box, L.cell, L.ccount);
             else
-                hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cmed, T, L.sst, L.st, L.cand, cap);
+                hipLaunchKernelGGL(k_med_cell<3>, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.box, L.cell, L.ccount);
+            hipLaunchKernelGGL(k_med_cell_scan, dim3(1), dim3(1024), 0, st, L.ccount);
+            hipLaunchKernelGGL(k_med_cell_scatter, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.cell, L.ccount, L.cs);
+            hipLaunchKernelGGL(k_med_group_box, dim3((ng + 3) / 4), dim3(256), 0, st, L.cs, T, L.gbox);
+            CT_CHECK_HIP(hipGetLastError());
+            const dim3 cgrid((ng + 255) / 256, ng), bgrid(kNumCU * 8);
+            const int nblk = (int)(cgrid.x * cgrid.y);
+            for (int pass = 0; pass < 2; ++pass) {
+                if (d == 2)
+                    hipLaunchKernelGGL(k_med_classify<2>, cgrid, dim3(256), 0, st, L.gbox, T, L.sst, pass, L.gcount, L.gbelow, L.glist);
+                else
+                    hipLaunchKernelGGL(k_med_classify<3>, cgrid, dim3(256), 0, st, L.gbox, T, L.sst, pass, L.gcount, L.gbelow, L.glist);
+                if (pass == 0)
+                    hipLaunchKernelGGL(k_med_list_scan, dim3(1), dim3(1024), 0, st, L.gcount, L.gbelow, nblk, L.st);
+            }
+            if (d == 2)
+                hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, L.cand, cap);
+            else
+                hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, L.cand, cap);
             hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(64), 0, st, L.st, T, cap);
             CT_CHECK_HIP(hipGetLastError());
             for (int pass = 0; pass < 3; ++pass) {

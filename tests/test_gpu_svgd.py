@@ -82,6 +82,28 @@ def test_bracketed_median_is_exact(ct, cfg, T):
     assert lt <= npair // 2 and le >= (npair + 1) // 2, (lt, le, npair)
 
 
+@pytest.mark.parametrize("d,T,spread", [(2, 30011, 0.01), (3, 12289, 0.02), (2, 24577, 0.2)])
+def test_box_settled_bracket_is_exact(ct, d, T, spread):
+    """Clustered samples (nine tight clusters: after the points are put in cell
+    order, the boxes of their groups of 64 settle most pairs of groups without
+    evaluating a pair), T not a multiple of 64, coordinates near 100: the pairs
+    strictly below / at most the returned median still straddle the middle ranks
+    (oracle pair counts).  The wide spread leaves more pairs of groups to the
+    pair-by-pair pass."""
+    rng = np.random.default_rng(T)
+    ctr = rng.uniform(0.0, 1.0, (9, d))
+    x = (100.0 + ctr[rng.integers(0, 9, T)] + rng.normal(0.0, spread, (T, d))).astype(np.float32)
+    g = W.gmm_params(np.random.default_rng(1), 2, d, 0.05, 0.1)
+    g.means[:] += 100.0
+    print(f"box-settled bracket d={d} T={T} spread={spread}", flush=True)
+    _phi, h, _sc = _gpu(ct, x, g)
+    med2 = h * np.log(T)
+    npair = T * (T - 1) // 2
+    lt, _ = oracle.pair_count(x, med2 * (1 - 2e-6))
+    _, le = oracle.pair_count(x, med2 * (1 + 2e-6))
+    assert lt <= npair // 2 and le >= (npair + 1) // 2, (lt, le, npair)
+
+
 def test_bracket_miss_falls_back_to_all_pairs(ct):
     # two coincident clusters of 10000 points: squared distances are 0 (99 990 000
     # pairs) or 0.5 (100 000 000 pairs), so the sampled bracket spans both values,
