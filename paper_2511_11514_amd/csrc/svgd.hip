@@ -109,7 +109,8 @@ struct MedState {
     float med;
     int mode;                    // 0: select over all pairs, 1: over the bracket's candidates
     unsigned long long below;    // pairs below the bracket
-    unsigned long long ncand;    // pairs inside the bracket (may exceed the buffer)
+    unsigned long long ncand;    // pairs inside the bracket (set by k_med_decide)
+    unsigned long long novf;     // of them appended to the shared overflow list
     unsigned nitems;             // pairs of groups listed for the pair-by-pair pass
 };
 
@@ -131,6 +132,22 @@ __host__ __device__ inline unsigned long long med_pairs(int T) {
 __host__ __device__ inline unsigned long long cand_cap(int T) {
     return (unsigned long long)(0.008 * (double)med_pairs(T)) + 65536ull;
 }
+
+// The pair-by-pair pass runs kBracketWaves waves; each owns a segment of the
+// candidate buffer (so that its appends need no atomic: one global counter
+// would serialise them), twice its share of cand_cap(T), and what overflows a
+// segment goes to a shared list of cand_cap(T) entries.
+constexpr int kBracketBlocks = kNumCU * 8;
+constexpr int kBracketWaves = kBracketBlocks * 4;
+__host__ __device__ inline unsigned long long cand_seg(int T) {
+    return (2 * cand_cap(T) + kBracketWaves - 1) / kBracketWaves;
+}
+
+struct CandStore {
+    float* cand;                 // [kBracketWaves][seg] segments, then [ovf_cap] shared overflow
+    unsigned* segcnt;            // [kBracketWaves] entries in each segment
+    unsigned long long seg, ovf_cap;
+};
 
 template <int D>
 __device__ __forceinline__ float sqdist(const float4& a, const float4& b) {
@@ -166,6 +183,7 @@ __global__ __launch_bounds__(256) void k_med_init(MedState* st, unsigned long lo
         st->mode = 0;
         st->below = 0ull;
         st->ncand = 0ull;
+        st->novf = 0ull;
         st->nitems = 0u;
     }
 }
@@ -480,20 +498,27 @@ __device__ __forceinline__ int box_class(const float4& alo, const float4& ahi, c
     return 0;
 }
 
-// Append the n candidates in buf (this wave's LDS buffer) to the global list,
-// one atomic for the wave.
-__device__ __forceinline__ void wave_append(const float* buf, unsigned n, MedState* st,
-                                            float* __restrict__ cand, unsigned long long cap,
-                                            int lane) {
+// Move the n candidates in buf (this wave's LDS buffer) to the wave's segment
+// (lc entries there so far), the part that does not fit to the shared overflow
+// list (one atomic for the wave).
+__device__ __forceinline__ void wave_append(const float* buf, unsigned n, const CandStore& C,
+                                            float* segp, unsigned& lc, MedState* st, int lane) {
     // the lanes read what other lanes of the wave wrote
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    unsigned long long base = 0ull;
-    if (lane == 0) base = atomicAdd(&st->ncand, (unsigned long long)n);
-    base = __shfl(base, 0, 64);
-    for (unsigned k = (unsigned)lane; k < n; k += 64)
-        if (base + k < cap) cand[base + k] = buf[k];
+    const unsigned room = lc < (unsigned)C.seg ? (unsigned)C.seg - lc : 0u;
+    const unsigned a = min(n, room);
+    for (unsigned k = (unsigned)lane; k < a; k += 64) segp[lc + k] = buf[k];
+    if (n > a) {
+        unsigned long long base = 0ull;
+        if (lane == 0) base = atomicAdd(&st->novf, (unsigned long long)(n - a));
+        base = __shfl(base, 0, 64);
+        float* ovf = C.cand + (size_t)kBracketWaves * C.seg;
+        for (unsigned k = a + (unsigned)lane; k < n; k += 64)
+            if (base + (k - a) < C.ovf_cap) ovf[base + (k - a)] = buf[k];
+    }
+    lc += a;
     // the buffer is refilled only after every lane has read it
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -525,12 +550,11 @@ __device__ __forceinline__ void bracket_pair(float d2, bool ok, unsigned lo, uns
 template <int D, bool CHECK>
 __device__ __forceinline__ void bracket_row(const float4* cj, int c0, int c1, int j0, const float4& xi,
                                             int ir, unsigned lo, unsigned span, unsigned& bl,
-                                            unsigned& nbuf, float* buf, MedState* st,
-                                            float* __restrict__ cand, unsigned long long cap,
-                                            int lane) {
+                                            unsigned& nbuf, float* buf, const CandStore& C,
+                                            float* segp, unsigned& lc, MedState* st, int lane) {
     for (int jj = c0; jj < c1; jj += 8) {
         if (nbuf > (unsigned)(kWaveBuf - 8 * 64)) {
-            wave_append(buf, nbuf, st, cand, cap, lane);
+            wave_append(buf, nbuf, C, segp, lc, st, lane);
             nbuf = 0u;
         }
         float4 xj[8];
@@ -664,8 +688,7 @@ template <int D>
 __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ cs,
                                                      const unsigned* __restrict__ list, int T,
                                                      const MedState* __restrict__ sst,
-                                                     MedState* st, float* __restrict__ cand,
-                                                     unsigned long long cap) {
+                                                     MedState* st, CandStore C) {
     __shared__ float4 cjw[4][kBoxPts];
     __shared__ float wbuf[4][kWaveBuf];
     const int lane = (int)threadIdx.x & 63;
@@ -680,10 +703,12 @@ __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ 
     // the wave's k-th pair of groups is list[first + k nw]; lane l holds entry
     // k = 64 q + l of batch q
     const int nmine = first < n ? (n - first + nw - 1) / nw : 0;
-    unsigned bl = 0u, nbuf = 0u;
+    unsigned bl = 0u, nbuf = 0u, lc = 0u;
+    float* segp = C.cand + (size_t)first * C.seg;
     unsigned batch = 0u;
     if (lane < nmine) batch = list[first + lane * nw];
-    unsigned item = __shfl(batch, 0, 64);
+    // wave-uniform: the loops below run on scalar bounds
+    unsigned item = __builtin_amdgcn_readfirstlane(__shfl(batch, 0, 64));
     float4 xr = make_float4(0.f, 0.f, 0.f, 0.f), xc = xr;
     if (nmine > 0) {
         xr = cs[min((int)(item & 0xFFFFu) * kBoxPts + lane, T - 1)];
@@ -702,7 +727,7 @@ __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ 
                 const int q = k + 1 + lane;
                 batch = q < nmine ? list[first + q * nw] : 0u;
             }
-            item = __shfl(batch, (k + 1) & 63, 64);
+            item = __builtin_amdgcn_readfirstlane(__shfl(batch, (k + 1) & 63, 64));
             xr = cs[min((int)(item & 0xFFFFu) * kBoxPts + lane, T - 1)];
             xc = cs[min((int)(item >> 16) * kBoxPts + lane, T - 1)];
         }
@@ -710,17 +735,18 @@ __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ 
         // rows past the end take j > T, which no column satisfies
         const int ir = min(kBoxPts * gr + lane, T);
         if (gr == gc)
-            bracket_row<D, true>(cw, 0, ncols, kBoxPts * gc, xi, ir, lo, span, bl, nbuf, buf, st, cand,
-                                 cap, lane);
+            bracket_row<D, true>(cw, 0, ncols, kBoxPts * gc, xi, ir, lo, span, bl, nbuf, buf, C, segp,
+                                 lc, st, lane);
         else
-            bracket_row<D, false>(cw, 0, ncols, kBoxPts * gc, xi, ir, lo, span, bl, nbuf, buf, st,
-                                  cand, cap, lane);
+            bracket_row<D, false>(cw, 0, ncols, kBoxPts * gc, xi, ir, lo, span, bl, nbuf, buf, C, segp,
+                                  lc, st, lane);
         // the columns are overwritten only after every lane has read them
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (nbuf) wave_append(buf, nbuf, st, cand, cap, lane);
+    if (nbuf) wave_append(buf, nbuf, C, segp, lc, st, lane);
+    if (lane == 0) C.segcnt[first] = lc;
     // pairs below the bracket: a wave sum, then one atomic per wave
     unsigned long long b = bl;
 #pragma unroll
@@ -728,13 +754,26 @@ __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ 
     if (lane == 0 && b) atomicAdd(&st->below, b);
 }
 
-// Use the candidates if both targets fall inside the bracket and none was lost.
-__global__ __launch_bounds__(64) void k_med_decide(MedState* st, int T, unsigned long long cap) {
+// Count the candidates (the segments' counts and the overflow appends); use
+// them if both targets fall inside the bracket and none was lost.
+__global__ __launch_bounds__(1024) void k_med_decide(MedState* st, int T, const unsigned* __restrict__ segcnt,
+                                                     unsigned long long ovf_cap) {
+    __shared__ unsigned long long wsum[16];
+    unsigned long long c = 0ull;
+    for (int w = threadIdx.x; w < kBracketWaves; w += 1024) c += segcnt[w];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    const unsigned long long novf = st->novf;
+    unsigned long long nc = novf;
+    for (int w = 0; w < 16; ++w) nc += wsum[w];
+    st->ncand = nc;
     const unsigned long long n = med_pairs(T);
     const unsigned long long ra = n ? (n - 1) / 2 : 0, rb = n / 2;
-    const unsigned long long below = st->below, nc = st->ncand;
-    if (nc <= cap && below <= ra && rb < below + nc) {
+    const unsigned long long below = st->below;
+    if (novf <= ovf_cap && below <= ra && rb < below + nc) {
         st->mode = 1;
         st->rank[0] = ra - below;
         st->rank[1] = rb - below;
@@ -744,6 +783,44 @@ __global__ __launch_bounds__(64) void k_med_decide(MedState* st, int T, unsigned
         st->rank[1] = rb;
     }
     st->prefix[0] = st->prefix[1] = 0u;
+}
+
+// The histogram of k_flat_hist over the candidates: each segment's entries, then
+// the overflow list's.  Runs only when st->mode == 1.
+__global__ __launch_bounds__(256) void k_cand_hist(CandStore C, int pass, const MedState* st,
+                                                   unsigned long long* __restrict__ hist) {
+    __shared__ unsigned h[2][kMedBins];
+    if (st->mode != 1) return;
+    const MedPass P = med_pass(pass);
+    const unsigned pa = st->prefix[0], pb = st->prefix[1];
+    const bool two = pa != pb;
+    const int nb = 1 << P.bits;
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        h[0][k] = 0u;
+        h[1][k] = 0u;
+    }
+    __syncthreads();
+    auto add = [&](float v) {
+        const unsigned u = __float_as_uint(v);
+        const unsigned bin = (u >> P.shift) & (unsigned)(nb - 1);
+        if ((u & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
+        if (two && (u & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
+    };
+    for (int w = blockIdx.x; w < kBracketWaves; w += gridDim.x) {
+        const float* v = C.cand + (size_t)w * C.seg;
+        const unsigned n = C.segcnt[w];
+        for (unsigned k = threadIdx.x; k < n; k += 256) add(v[k]);
+    }
+    const float* ovf = C.cand + (size_t)kBracketWaves * C.seg;
+    const unsigned long long no = min(st->novf, C.ovf_cap);
+    for (unsigned long long k = (unsigned long long)blockIdx.x * 256 + threadIdx.x; k < no;
+         k += (unsigned long long)gridDim.x * 256)
+        add(ovf[k]);
+    __syncthreads();
+    for (int k = threadIdx.x; k < nb; k += 256) {
+        if (h[0][k]) atomicAdd(&hist[k], (unsigned long long)h[0][k]);
+        if (two && h[1][k]) atomicAdd(&hist[kMedBins + k], (unsigned long long)h[1][k]);
+    }
 }
 
 // Locate each target's bin, extend its prefix, clear the histograms.  Each
@@ -1030,7 +1107,8 @@ struct SvLayout {
     MedState* st;
     MedState* sst;     // selection state of the bracket's sample (large T)
     float* samp;       // [kMedSample] sampled squared distances (large T)
-    float* cand;       // [cand_cap(T)] squared distances inside the bracket (large T)
+    float* cand;       // [kBracketWaves cand_seg(T) + cand_cap(T)] squared distances inside the bracket (large T)
+    unsigned* segcnt;  // [kBracketWaves] candidates in each wave's segment (large T)
     unsigned long long* hist;
     float* score;
     float4* cmed;      // raw coordinates for the median
@@ -1074,7 +1152,8 @@ static SvLayout sv_layout(void* ws, int T, int d) {
     // the bracket's buffers exist only where a median can be asked for
     const bool bracket = T >= kBracketMinT && T <= kMaxMedianT;
     L.samp = bracket ? a.take<float>(kMedSample) : nullptr;
-    L.cand = bracket ? a.take<float>((size_t)cand_cap(T)) : nullptr;
+    L.cand = bracket ? a.take<float>((size_t)(kBracketWaves * cand_seg(T) + cand_cap(T))) : nullptr;
+    L.segcnt = bracket ? a.take<unsigned>(kBracketWaves) : nullptr;
     L.score = a.take<float>((size_t)T * d);
     L.cmed = a.take<float4>(T);
     L.box = bracket ? a.take<float4>(2) : nullptr;
@@ -1165,7 +1244,7 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
             hipLaunchKernelGGL(k_med_cell_scatter, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.cell, L.ccount, L.cs);
             hipLaunchKernelGGL(k_med_group_box, dim3((ng + 3) / 4), dim3(256), 0, st, L.cs, T, L.gbox);
             CT_CHECK_HIP(hipGetLastError());
-            const dim3 cgrid((ng + 255) / 256, ng), bgrid(kNumCU * 8);
+            const dim3 cgrid((ng + 255) / 256, ng), bgrid(kBracketBlocks);
             const int nblk = (int)(cgrid.x * cgrid.y);
             for (int pass = 0; pass < 2; ++pass) {
                 if (d == 2)
@@ -1175,15 +1254,19 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
                 if (pass == 0)
                     hipLaunchKernelGGL(k_med_list_scan, dim3(1), dim3(1024), 0, st, L.gcount, L.gbelow, nblk, L.st);
             }
+            CandStore C;
+            C.cand = L.cand;
+            C.segcnt = L.segcnt;
+            C.seg = cand_seg(T);
+            C.ovf_cap = cap;
             if (d == 2)
-                hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, L.cand, cap);
+                hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
             else
-                hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, L.cand, cap);
-            hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(64), 0, st, L.st, T, cap);
+                hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
+            hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(1024), 0, st, L.st, T, L.segcnt, cap);
             CT_CHECK_HIP(hipGetLastError());
             for (int pass = 0; pass < 3; ++pass) {
-                hipLaunchKernelGGL(k_flat_hist, dim3(1024), dim3(256), 0, st, L.cand, 0,
-                                   reinterpret_cast<const unsigned long long*>(reinterpret_cast<const char*>(L.st) + offsetof(MedState, ncand)), cap, pass, L.st, 1, L.hist);
+                hipLaunchKernelGGL(k_cand_hist, dim3(1024), dim3(256), 0, st, C, pass, L.st, L.hist);
                 hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.st, L.hist, pass, T, 1, 1);
                 CT_CHECK_HIP(hipGetLastError());
             }
