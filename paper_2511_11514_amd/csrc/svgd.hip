@@ -800,11 +800,23 @@ __global__ __launch_bounds__(256) void k_cand_hist(CandStore C, int pass, const 
         h[1][k] = 0u;
     }
     __syncthreads();
+    // Candidates lie inside the bracket, so most of a wave's values share a bin
+    // (all of them in the first pass, whose 12 bits are coarser than the
+    // bracket): the lanes in the bin of the wave's first active lane add one
+    // count together, the others one each.
+    const int lane = (int)threadIdx.x & 63;
     auto add = [&](float v) {
         const unsigned u = __float_as_uint(v);
         const unsigned bin = (u >> P.shift) & (unsigned)(nb - 1);
-        if ((u & P.fixed_mask) == pa) atomicAdd(&h[0][bin], 1u);
-        if (two && (u & P.fixed_mask) == pb) atomicAdd(&h[1][bin], 1u);
+        const unsigned b0 = __builtin_amdgcn_readfirstlane(bin);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            if (t == 1 && !two) break;
+            const bool mine = (u & P.fixed_mask) == (t ? pb : pa);
+            const unsigned long long m = __builtin_amdgcn_ballot_w64(mine && bin == b0);
+            if (m && lane == __builtin_ctzll(m)) atomicAdd(&h[t][b0], (unsigned)__popcll(m));
+            if (mine && bin != b0) atomicAdd(&h[t][bin], 1u);
+        }
     };
     for (int w = blockIdx.x; w < kBracketWaves; w += gridDim.x) {
         const float* v = C.cand + (size_t)w * C.seg;
