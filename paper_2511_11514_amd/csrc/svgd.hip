@@ -112,6 +112,7 @@ struct MedState {
     unsigned long long ncand;    // pairs inside the bracket (set by k_med_decide)
     unsigned long long novf;     // of them appended to the shared overflow list
     unsigned nitems;             // pairs of groups listed for the pair-by-pair pass
+    int skip0;                   // the candidates share the first pass's bits: it is skipped
 };
 
 // Large T: an exact selection over a bracket.  kMedSample pseudo-random pairs
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(256) void k_med_init(MedState* st, unsigned long lo
         st->ncand = 0ull;
         st->novf = 0ull;
         st->nitems = 0u;
+        st->skip0 = 0;
     }
 }
 
@@ -755,8 +757,12 @@ __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ 
 }
 
 // Count the candidates (the segments' counts and the overflow appends); use
-// them if both targets fall inside the bracket and none was lost.
-__global__ __launch_bounds__(1024) void k_med_decide(MedState* st, int T, const unsigned* __restrict__ segcnt,
+// them if both targets fall inside the bracket and none was lost.  When the
+// bracket's ends agree on the first pass's bits (30..19), so does every
+// candidate: the first pass over them would only find that bin, so its prefix
+// is set here and the pass skipped.
+__global__ __launch_bounds__(1024) void k_med_decide(MedState* st, const MedState* __restrict__ sst,
+                                                     int T, const unsigned* __restrict__ segcnt,
                                                      unsigned long long ovf_cap) {
     __shared__ unsigned long long wsum[16];
     unsigned long long c = 0ull;
@@ -773,16 +779,23 @@ __global__ __launch_bounds__(1024) void k_med_decide(MedState* st, int T, const 
     const unsigned long long n = med_pairs(T);
     const unsigned long long ra = n ? (n - 1) / 2 : 0, rb = n / 2;
     const unsigned long long below = st->below;
+    const unsigned first = med_pass(1).fixed_mask;           // bits 30..19
+    const unsigned lo = sst->prefix[0], hi = sst->prefix[1];
+    st->prefix[0] = st->prefix[1] = 0u;
+    st->skip0 = 0;
     if (novf <= ovf_cap && below <= ra && rb < below + nc) {
         st->mode = 1;
         st->rank[0] = ra - below;
         st->rank[1] = rb - below;
+        if (((lo ^ hi) & first) == 0u) {
+            st->prefix[0] = st->prefix[1] = lo & first;
+            st->skip0 = 1;
+        }
     } else {
         st->mode = 0;
         st->rank[0] = ra;
         st->rank[1] = rb;
     }
-    st->prefix[0] = st->prefix[1] = 0u;
 }
 
 // The histogram of k_flat_hist over the candidates: each segment's entries, then
@@ -790,7 +803,7 @@ __global__ __launch_bounds__(1024) void k_med_decide(MedState* st, int T, const 
 __global__ __launch_bounds__(256) void k_cand_hist(CandStore C, int pass, const MedState* st,
                                                    unsigned long long* __restrict__ hist) {
     __shared__ unsigned h[2][kMedBins];
-    if (st->mode != 1) return;
+    if (st->mode != 1 || (pass == 0 && st->skip0)) return;
     const MedPass P = med_pass(pass);
     const unsigned pa = st->prefix[0], pb = st->prefix[1];
     const bool two = pa != pb;
@@ -845,6 +858,7 @@ __global__ __launch_bounds__(256) void k_med_select(MedState* st, unsigned long 
                                                     int pass, int T, int gate, int finish) {
     __shared__ unsigned long long wsum[4];
     if (gate >= 0 && st->mode != gate) return;
+    if (gate == 1 && pass == 0 && st->skip0) return;       // prefix set by k_med_decide
     const MedPass P = med_pass(pass);
     const int nb = 1 << P.bits;
     const int per = nb / 256;          // bins per thread (16, 8 or 1)
@@ -1275,7 +1289,7 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
                 hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
             else
                 hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
-            hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(1024), 0, st, L.st, T, L.segcnt, cap);
+            hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(1024), 0, st, L.st, L.sst, T, L.segcnt, cap);
             CT_CHECK_HIP(hipGetLastError());
             for (int pass = 0; pass < 3; ++pass) {
                 hipLaunchKernelGGL(k_cand_hist, dim3(1024), dim3(256), 0, st, C, pass, L.st, L.hist);
