@@ -291,16 +291,11 @@ __global__ __launch_bounds__(256) void k_med_hist(const float4* __restrict__ c, 
     }
 }
 
-// The same histogram over a flat array of squared distances: n0 values, or
-// min(*count, cap) when count is given.  Runs only when gate < 0 or st->mode == gate.
-__global__ __launch_bounds__(256) void k_flat_hist(const float* __restrict__ v, int n0,
-                                                   const unsigned long long* count,
-                                                   unsigned long long cap, int pass,
-                                                   const MedState* st, int gate,
+// The same histogram over a flat array of n squared distances (the bracket's sample).
+__global__ __launch_bounds__(256) void k_flat_hist(const float* __restrict__ v, int n, int pass,
+                                                   const MedState* st,
                                                    unsigned long long* __restrict__ hist) {
     __shared__ unsigned h[2][kMedBins];
-    if (gate >= 0 && st->mode != gate) return;
-    const long long n = count ? (long long)min(*count, cap) : (long long)n0;
     const MedPass P = med_pass(pass);
     const unsigned pa = st->prefix[0], pb = st->prefix[1];
     const bool two = pa != pb;
@@ -1253,8 +1248,7 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
                 hipLaunchKernelGGL(k_med_sample<3>, dim3(kMedSample / 256), dim3(256), 0, st, L.cmed, T, L.samp);
             CT_CHECK_HIP(hipGetLastError());
             for (int pass = 0; pass < 3; ++pass) {
-                hipLaunchKernelGGL(k_flat_hist, dim3(1024), dim3(256), 0, st, L.samp, kMedSample,
-                                   (const unsigned long long*)nullptr, 0ull, pass, L.sst, -1, L.hist);
+                hipLaunchKernelGGL(k_flat_hist, dim3(1024), dim3(256), 0, st, L.samp, kMedSample, pass, L.sst, L.hist);
                 hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.sst, L.hist, pass, T, -1, 0);
                 CT_CHECK_HIP(hipGetLastError());
             }

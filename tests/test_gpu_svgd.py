@@ -69,7 +69,8 @@ def test_degenerate_cases(ct):
     np.testing.assert_allclose(phi, sc, rtol=1e-6)
 
 
-@pytest.mark.parametrize("cfg,T", [("grad_2d", 20000), ("autograd_3d", 17000)])
+@pytest.mark.parametrize("cfg,T", [("grad_2d", 20000), ("autograd_3d", 17000), ("grad_2d", 11000),
+                                   ("roofline_2d", 92681)])
 def test_bracketed_median_is_exact(ct, cfg, T):
     # large T: the median comes from a sampled bracket and one pass over all pairs;
     # the pairs strictly below / at most the returned median must straddle the middle ranks
