@@ -331,11 +331,9 @@ __global__ __launch_bounds__(256) void k_flat_hist(const float* __restrict__ v, 
 // is monotonic, so they bound every pair's float32 value exactly; a box with a
 // non-finite coordinate is NaN and its groups are always evaluated.  The
 // unordered pairs {i, j} and their values are those of the original order.
-constexpr int kBoxPts = 64;                       // points per box: a wave's rows, a quarter tile's columns
+constexpr int kBoxPts = 64;                      // points per box: a wave's rows or columns
 constexpr int kWaveBuf = 960;                    // candidates a wave holds in LDS (8 blocks per CU)
 constexpr int kCells2 = 1 << 15;                 // cell counts: 128 x 128 cells (2-D), 32 x 32 x 32 (3-D)
-
-
 
 __global__ __launch_bounds__(256) void k_fill_u32(unsigned* __restrict__ p, int n, unsigned v) {
     const int i = blockIdx.x * 256 + (int)threadIdx.x;
