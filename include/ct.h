@@ -311,10 +311,10 @@ typedef struct ct_gmm {
 } ct_gmm;
 
 /* Workspace of ct_svgd_grad / ct_svgd_grad_score: O(T) bytes, plus, for 11000 <= T <= 92681
- * (median bandwidth over a sampled bracket), 4 MiB of samples, 4 bytes per pair of 64-point
- * groups, and 12 bytes per 125 pairs for the bracket's candidates (each wave of the pass owns a
- * segment of twice its share, a shared overflow list holds the rest): 235 MB in all at
- * T = 65536, 447 MB at T = 92681. */
+ * (median bandwidth over a sampled bracket), 4 MiB of samples and 4 bytes per 125 pairs for the
+ * bracket's candidates; from T = 24576 on also 4 bytes per pair of 64-point groups and another
+ * 8 bytes per 125 pairs (each wave of the pass owns a segment of twice its share of the
+ * candidates): 245 MB in all at T = 65536 (d = 3), 458 MB at T = 92681. */
 size_t ct_svgd_workspace_size(int64_t T, int32_t d);
 
 /*

@@ -142,8 +142,11 @@ __host__ __device__ inline unsigned long long cand_cap(int T) {
 // segment goes to a shared list of cand_cap(T) entries.
 constexpr int kBracketBlocks = kNumCU * 8;
 constexpr int kBracketWaves = kBracketBlocks * 4;
+// From this T on the pass runs over boxes of point groups; below it over every
+// pair in tiles, with all candidates in the shared list (no segments).
+constexpr int kBoxMinT = 24576;
 __host__ __device__ inline unsigned long long cand_seg(int T) {
-    return (2 * cand_cap(T) + kBracketWaves - 1) / kBracketWaves;
+    return T >= kBoxMinT ? (2 * cand_cap(T) + kBracketWaves - 1) / kBracketWaves : 0ull;
 }
 
 struct CandStore {
@@ -318,6 +321,127 @@ __global__ __launch_bounds__(256) void k_flat_hist(const float* __restrict__ v, 
         if (h[0][k]) atomicAdd(&hist[k], (unsigned long long)h[0][k]);
         if (two && h[1][k]) atomicAdd(&hist[kMedBins + k], (unsigned long long)h[1][k]);
     }
+}
+
+constexpr int kCandSlots = 16;
+constexpr int kBracketRows = 4;                  // rows per thread: tiles of 1024 x 256
+
+inline int bracket_tile_grid(int T) {
+    const int ntr = (T + 256 * kBracketRows - 1) / (256 * kBracketRows), ntc = (T + 255) / 256;
+    return std::min(ntr * ntc, kNumCU * 8);
+}
+
+// The pairs of one tile of the pass over every pair: count those below the
+// bracket, keep those in it (the first kCandSlots per thread in LDS slots, the
+// rest straight to the shared candidate list).  CHECK keeps only pairs with
+// j > i (diagonal and ragged tiles).
+template <int D, int RB, bool CHECK>
+__device__ __forceinline__ void bracket_tile_pairs(const float4* cj, int n, int j0, const float4 (&xi)[RB],
+                                              const int (&ir)[RB], unsigned lo, unsigned span,
+                                              unsigned& bl, unsigned& nin,
+                                              float (*slots)[256], MedState* st,
+                                              float* __restrict__ cand, unsigned long long cap) {
+    for (int jj = 0; jj < n; jj += 8) {
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+            const int jl = jj + g;
+            if (jl < n) {
+                const float4 xj = cj[jl];
+                const int j = j0 + jl;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    const float d2 = sqdist<D>(xi[r], xj);
+                    const unsigned u = __float_as_uint(d2);
+                    const bool ok = !CHECK || j > ir[r];
+                    bl += (ok && u < lo) ? 1u : 0u;
+                    if (ok && u - lo <= span) {
+                        if (nin < (unsigned)kCandSlots) {
+                            slots[nin][threadIdx.x] = d2;
+                        } else {
+                            const unsigned long long gi = atomicAdd(&st->novf, 1ull);
+                            if (gi < cap) cand[gi] = d2;
+                        }
+                        ++nin;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The pass over every pair in the original order, for T below kBoxMinT (where
+// ordering the points and their boxes costs more than they save): tiles of
+// 1024 rows (four per thread) by 256 LDS-staged columns; the candidates go to
+// the shared list (cand, cap entries; st->novf counts them), one append per
+// block and tile.
+template <int D>
+__global__ __launch_bounds__(256) void k_med_bracket_tiles(const float4* __restrict__ c, int T,
+                                                           const MedState* __restrict__ sst,
+                                                           MedState* st, float* __restrict__ cand,
+                                                           unsigned long long cap) {
+    constexpr int RB = kBracketRows;
+    __shared__ float4 cj[256];
+    __shared__ float slots[kCandSlots][256];
+    __shared__ unsigned wsum[4];
+    __shared__ unsigned long long base;
+    const int ntr = (T + 256 * RB - 1) / (256 * RB), ntc = (T + 255) / 256;
+    const int ntiles = ntr * ntc;
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const unsigned lo = sst->prefix[0], hi = sst->prefix[1];
+    const unsigned span = hi - lo;                 // u in [lo, hi]  <=>  u - lo <= span
+    unsigned long long below = 0ull;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int i0 = (t % ntr) * 256 * RB;
+        const int j0 = (t / ntr) * 256;
+        const int j1 = min(T, j0 + 256);
+        if (j1 - 1 <= i0) continue;               // no column j > any row i of the tile
+        __syncthreads();                           // previous tile: columns and slots consumed
+        if ((int)threadIdx.x < j1 - j0) cj[threadIdx.x] = c[j0 + threadIdx.x];
+        __syncthreads();
+        float4 xi[RB];
+        int ir[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            ir[r] = i0 + r * 256 + (int)threadIdx.x;
+            // rows past the end take j > T, which no column satisfies
+            xi[r] = ir[r] < T ? c[ir[r]] : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ir[r] >= T) ir[r] = T;
+        }
+        unsigned nin = 0u, bl = 0u;
+        const int n = j1 - j0;
+        // every row valid and below every column of the tile: no pair needs j > i
+        const bool off_diag = i0 + 256 * RB <= T && j0 >= i0 + 256 * RB;
+        if (off_diag)
+            bracket_tile_pairs<D, RB, false>(cj, n, j0, xi, ir, lo, span, bl, nin, slots, st, cand, cap);
+        else
+            bracket_tile_pairs<D, RB, true>(cj, n, j0, xi, ir, lo, span, bl, nin, slots, st, cand, cap);
+        below += bl;
+        // block exclusive prefix sum of the kept counts
+        const unsigned kept = min(nin, (unsigned)kCandSlots);
+        unsigned inc = kept;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned v = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += v;
+        }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        unsigned before = 0u, total = 0u;
+        for (int w = 0; w < 4; ++w) {
+            before += w < wave ? wsum[w] : 0u;
+            total += wsum[w];
+        }
+        if (threadIdx.x == 0) base = total ? atomicAdd(&st->novf, (unsigned long long)total) : 0ull;
+        __syncthreads();
+        const unsigned long long off = base + before + inc - kept;
+        for (unsigned k = 0; k < kept; ++k)
+            if (off + k < cap) cand[off + k] = slots[k][threadIdx.x];
+    }
+    // pairs below the bracket: a wave sum, then one atomic per wave
+    unsigned long long b = below;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) b += __shfl_down(b, o, 64);
+    if (lane == 0 && b) atomicAdd(&st->below, b);
 }
 
 // One pass over all pairs i < j: count the pairs below the bracket [lo, hi]
@@ -1177,16 +1301,17 @@ static SvLayout sv_layout(void* ws, int T, int d) {
     L.segcnt = bracket ? a.take<unsigned>(kBracketWaves) : nullptr;
     L.score = a.take<float>((size_t)T * d);
     L.cmed = a.take<float4>(T);
-    L.box = bracket ? a.take<float4>(2) : nullptr;
-    L.cell = bracket ? a.take<unsigned>(T) : nullptr;
-    L.ccount = bracket ? a.take<unsigned>(kCells2) : nullptr;
-    L.cs = bracket ? a.take<float4>(T) : nullptr;
+    const bool boxes = bracket && T >= kBoxMinT;
+    L.box = boxes ? a.take<float4>(2) : nullptr;
+    L.cell = boxes ? a.take<unsigned>(T) : nullptr;
+    L.ccount = boxes ? a.take<unsigned>(kCells2) : nullptr;
+    L.cs = boxes ? a.take<float4>(T) : nullptr;
     const size_t ngrp = (size_t)((T + kBoxPts - 1) / kBoxPts);
-    L.gbox = bracket ? a.take<float4>(2 * ngrp) : nullptr;
-    L.glist = bracket ? a.take<unsigned>(ngrp * (ngrp + 1) / 2) : nullptr;
+    L.gbox = boxes ? a.take<float4>(2 * ngrp) : nullptr;
+    L.glist = boxes ? a.take<unsigned>(ngrp * (ngrp + 1) / 2) : nullptr;
     const size_t nblk = ngrp * ((ngrp + 255) / 256);
-    L.gcount = bracket ? a.take<unsigned>(nblk) : nullptr;
-    L.gbelow = bracket ? a.take<unsigned long long>(nblk) : nullptr;
+    L.gcount = boxes ? a.take<unsigned>(nblk) : nullptr;
+    L.gbelow = boxes ? a.take<unsigned long long>(nblk) : nullptr;
     L.origin = a.take<float>(4);
     L.qc = a.take<float4>(T);
     L.krec = a.take<float4>((size_t)Tpad * (d == 2 ? 1 : 2));
@@ -1252,37 +1377,49 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
                 hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, L.sst, L.hist, pass, T, -1, 0);
                 CT_CHECK_HIP(hipGetLastError());
             }
-            // the points in Morton-cell order and the boxes of their groups
-            const int ng = (T + kBoxPts - 1) / kBoxPts;
-            hipLaunchKernelGGL(k_fill_u32, dim3(kCells2 / 256), dim3(256), 0, st, L.ccount, kCells2, 0u);
-            hipLaunchKernelGGL(k_med_box, dim3(1), dim3(1024), 0, st, L.cmed, T, L.box);
-            if (d == 2)
-                hipLaunchKernelGGL(k_med_cell<2>, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.box, L.cell, L.ccount);
-            else
-                hipLaunchKernelGGL(k_med_cell<3>, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.box, L.cell, L.ccount);
-            hipLaunchKernelGGL(k_med_cell_scan, dim3(1), dim3(1024), 0, st, L.ccount);
-            hipLaunchKernelGGL(k_med_cell_scatter, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.cell, L.ccount, L.cs);
-            hipLaunchKernelGGL(k_med_group_box, dim3((ng + 3) / 4), dim3(256), 0, st, L.cs, T, L.gbox);
-            CT_CHECK_HIP(hipGetLastError());
-            const dim3 cgrid((ng + 255) / 256, ng), bgrid(kBracketBlocks);
-            const int nblk = (int)(cgrid.x * cgrid.y);
-            for (int pass = 0; pass < 2; ++pass) {
-                if (d == 2)
-                    hipLaunchKernelGGL(k_med_classify<2>, cgrid, dim3(256), 0, st, L.gbox, T, L.sst, pass, L.gcount, L.gbelow, L.glist);
-                else
-                    hipLaunchKernelGGL(k_med_classify<3>, cgrid, dim3(256), 0, st, L.gbox, T, L.sst, pass, L.gcount, L.gbelow, L.glist);
-                if (pass == 0)
-                    hipLaunchKernelGGL(k_med_list_scan, dim3(1), dim3(1024), 0, st, L.gcount, L.gbelow, nblk, L.st);
-            }
             CandStore C;
             C.cand = L.cand;
             C.segcnt = L.segcnt;
             C.seg = cand_seg(T);
             C.ovf_cap = cap;
-            if (d == 2)
-                hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
-            else
-                hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
+            if (T < kBoxMinT) {
+                // every pair in the original order; all candidates in the shared list
+                hipLaunchKernelGGL(k_fill_u32, dim3(kBracketWaves / 256), dim3(256), 0, st, L.segcnt, kBracketWaves, 0u);
+                float* ovf = L.cand + (size_t)kBracketWaves * C.seg;
+                const dim3 tgrid(bracket_tile_grid(T));
+                if (d == 2)
+                    hipLaunchKernelGGL(k_med_bracket_tiles<2>, tgrid, dim3(256), 0, st, L.cmed, T, L.sst, L.st, ovf, cap);
+                else
+                    hipLaunchKernelGGL(k_med_bracket_tiles<3>, tgrid, dim3(256), 0, st, L.cmed, T, L.sst, L.st, ovf, cap);
+                CT_CHECK_HIP(hipGetLastError());
+            } else {
+                // the points in Morton-cell order and the boxes of their groups
+                const int ng = (T + kBoxPts - 1) / kBoxPts;
+                hipLaunchKernelGGL(k_fill_u32, dim3(kCells2 / 256), dim3(256), 0, st, L.ccount, kCells2, 0u);
+                hipLaunchKernelGGL(k_med_box, dim3(1), dim3(1024), 0, st, L.cmed, T, L.box);
+                if (d == 2)
+                    hipLaunchKernelGGL(k_med_cell<2>, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.box, L.cell, L.ccount);
+                else
+                    hipLaunchKernelGGL(k_med_cell<3>, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.box, L.cell, L.ccount);
+                hipLaunchKernelGGL(k_med_cell_scan, dim3(1), dim3(1024), 0, st, L.ccount);
+                hipLaunchKernelGGL(k_med_cell_scatter, dim3((T + 255) / 256), dim3(256), 0, st, L.cmed, T, L.cell, L.ccount, L.cs);
+                hipLaunchKernelGGL(k_med_group_box, dim3((ng + 3) / 4), dim3(256), 0, st, L.cs, T, L.gbox);
+                CT_CHECK_HIP(hipGetLastError());
+                const dim3 cgrid((ng + 255) / 256, ng), bgrid(kBracketBlocks);
+                const int nblk = (int)(cgrid.x * cgrid.y);
+                for (int pass = 0; pass < 2; ++pass) {
+                    if (d == 2)
+                        hipLaunchKernelGGL(k_med_classify<2>, cgrid, dim3(256), 0, st, L.gbox, T, L.sst, pass, L.gcount, L.gbelow, L.glist);
+                    else
+                        hipLaunchKernelGGL(k_med_classify<3>, cgrid, dim3(256), 0, st, L.gbox, T, L.sst, pass, L.gcount, L.gbelow, L.glist);
+                    if (pass == 0)
+                        hipLaunchKernelGGL(k_med_list_scan, dim3(1), dim3(1024), 0, st, L.gcount, L.gbelow, nblk, L.st);
+                }
+                if (d == 2)
+                    hipLaunchKernelGGL(k_med_bracket<2>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
+                else
+                    hipLaunchKernelGGL(k_med_bracket<3>, bgrid, dim3(256), 0, st, L.cs, L.glist, T, L.sst, L.st, C);
+            }
             hipLaunchKernelGGL(k_med_decide, dim3(1), dim3(1024), 0, st, L.st, L.sst, T, L.segcnt, cap);
             CT_CHECK_HIP(hipGetLastError());
             for (int pass = 0; pass < 3; ++pass) {
