@@ -14,10 +14,12 @@
 //                 patterns (12 + 11 + 8 bits), both middle ranks tracked so an
 //                 even count takes the mean of the two middle distances; for
 //                 large T the same selection runs over the pairs inside a
-//                 bracket found on a sample (k_med_sample / k_med_bracket, the
-//                 points in Morton-cell order so that bounding boxes of groups
-//                 of 64 settle most pairs of groups, k_med_classify), with the
-//                 full selection as the fallback;
+//                 bracket found on a sample (k_med_sample, then one pass over
+//                 the pairs: k_med_bracket_tiles over every pair, or from
+//                 T = kBoxMinT k_med_bracket with the points in Morton-cell
+//                 order so that bounding boxes of groups of 64 settle most pairs
+//                 of groups, k_med_classify), with the full selection as the
+//                 fallback;
 //   k_svgd_stage  bandwidth h = med^2 / ln T (or the caller's h), coordinates
 //                 pre-scaled by sqrt(log2(e)/h) so k_ij = 2^-|x'_i - x'_j|^2;
 //   k_svgd_sum / k_svgd_merge   the T x T sum, split over keys like the Sinkhorn
