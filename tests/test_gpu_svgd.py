@@ -70,10 +70,12 @@ def test_degenerate_cases(ct):
 
 
 @pytest.mark.parametrize("cfg,T", [("grad_2d", 20000), ("autograd_3d", 17000), ("grad_2d", 11000),
-                                   ("roofline_2d", 92681)])
+                                   ("roofline_2d", 92681), ("autograd_3d", 30001),
+                                   ("roofline_2d", 24576), ("roofline_2d", 24575)])
 def test_bracketed_median_is_exact(ct, cfg, T):
-    # large T: the median comes from a sampled bracket and one pass over all pairs;
-    # the pairs strictly below / at most the returned median must straddle the middle ranks
+    # large T: the median comes from a sampled bracket and one pass over all pairs (over
+    # every pair below T = 24576, over boxes of point groups from there on); the pairs
+    # strictly below / at most the returned median must straddle the middle ranks
     x, _y, _w, g = W.config_inputs(W.CONFIGS[cfg], T=T, M=16)
     _phi, h, _sc = _gpu(ct, x, g)
     med2 = h * np.log(T)
