@@ -1061,13 +1061,18 @@ __global__ __launch_bounds__(1024) void k_sv_origin(const float* __restrict__ x,
                                                     float* __restrict__ out) {
     __shared__ double red[4][1024];
     double s[3] = {0.0, 0.0, 0.0}, n = 0.0;
+    // a skipped sample adds zeros (no branch), so eight loads can be in flight
+#pragma unroll 8
     for (int i = threadIdx.x; i < T; i += 1024) {
         const float* p = x + (size_t)i * d;
+        float v[3] = {0.f, 0.f, 0.f};
         bool ok = true;
-        for (int t = 0; t < d; ++t) ok = ok && isfinite(p[t]);
-        if (!ok) continue;
-        for (int t = 0; t < d; ++t) s[t] += (double)p[t];
-        n += 1.0;
+        for (int t = 0; t < d; ++t) {
+            v[t] = p[t];
+            ok = ok && isfinite(v[t]);
+        }
+        for (int t = 0; t < d; ++t) s[t] += ok ? (double)v[t] : 0.0;
+        n += ok ? 1.0 : 0.0;
     }
     for (int t = 0; t < 3; ++t) red[t][threadIdx.x] = s[t];
     red[3][threadIdx.x] = n;
