@@ -1057,13 +1057,20 @@ struct KeyRec {
 // sqrt(log2(e)/h) is not translation invariant: far from the coordinate origin it
 // would round away the low bits of every difference.  Subtracting the mean first
 // (exact for nearby float32 values) keeps them.
-__global__ __launch_bounds__(1024) void k_sv_origin(const float* __restrict__ x, int T, int d,
-                                                    float* __restrict__ out) {
-    __shared__ double red[4][1024];
+constexpr int kSvOriginBlocks = 64;
+
+// Partial sums of the mean: block b sums the samples of its contiguous share in
+// a fixed order into part[b] = (sum x, sum y, sum z, count); k_svgd_stage adds
+// the kSvOriginBlocks partials in block order.
+__global__ __launch_bounds__(256) void k_sv_origin(const float* __restrict__ x, int T, int d,
+                                                   double* __restrict__ part) {
+    __shared__ double red[4][256];
+    const int chunk = (T + kSvOriginBlocks - 1) / kSvOriginBlocks;
+    const int i0 = (int)blockIdx.x * chunk, i1 = min(T, i0 + chunk);
     double s[3] = {0.0, 0.0, 0.0}, n = 0.0;
     // a skipped sample adds zeros (no branch), so eight loads can be in flight
 #pragma unroll 8
-    for (int i = threadIdx.x; i < T; i += 1024) {
+    for (int i = i0 + (int)threadIdx.x; i < i1; i += 256) {
         const float* p = x + (size_t)i * d;
         float v[3] = {0.f, 0.f, 0.f};
         bool ok = true;
@@ -1077,23 +1084,31 @@ __global__ __launch_bounds__(1024) void k_sv_origin(const float* __restrict__ x,
     for (int t = 0; t < 3; ++t) red[t][threadIdx.x] = s[t];
     red[3][threadIdx.x] = n;
     __syncthreads();
-    for (int h = 512; h > 0; h >>= 1) {
+    for (int h = 128; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
             for (int t = 0; t < 4; ++t) red[t][threadIdx.x] += red[t][threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x < 4) {
-        const double c = red[3][0] > 0.0 ? red[3][0] : 1.0;
-        out[threadIdx.x] = (int)threadIdx.x < d ? (float)(red[threadIdx.x][0] / c) : 0.f;
-    }
+    if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(256) void k_svgd_stage(const float* __restrict__ x,
                                                     const float* __restrict__ score, int T, int Tpad,
                                                     int d, float h_fixed, MedState* st,
-                                                    const float* __restrict__ origin,
+                                                    const double* __restrict__ opart,
                                                     float4* __restrict__ qc,
                                                     float4* __restrict__ krec) {
+    // the origin: the mean of k_sv_origin's partials, added in block order
+    __shared__ float origin[3];
+    if (threadIdx.x < 3) {
+        double a = 0.0, n = 0.0;
+        for (int b = 0; b < kSvOriginBlocks; ++b) {
+            a += opart[4 * b + threadIdx.x];
+            n += opart[4 * b + 3];
+        }
+        origin[threadIdx.x] = (int)threadIdx.x < d ? (float)(a / (n > 0.0 ? n : 1.0)) : 0.f;
+    }
+    __syncthreads();
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (h_fixed > 0.f && i == 0) st->h = h_fixed;
     const float h = h_fixed > 0.f ? h_fixed : st->h;
@@ -1272,7 +1287,7 @@ struct SvLayout {
     unsigned* glist;   // [ng (ng + 1) / 2] pairs of groups left to evaluate (large T)
     unsigned* gcount;  // [ng ceil(ng / 256)] per classifying block: listed pairs, then offsets
     unsigned long long* gbelow;  // [same] per classifying block: pairs below the bracket
-    float* origin;     // [4] mean of the samples, subtracted before the bandwidth scale
+    double* origin;    // [4 kSvOriginBlocks] partial sums of the mean, subtracted before the bandwidth scale
     float4* qc;
     float4* krec;
     float* part;
@@ -1319,7 +1334,7 @@ static SvLayout sv_layout(void* ws, int T, int d) {
     const size_t nblk = ngrp * ((ngrp + 255) / 256);
     L.gcount = boxes ? a.take<unsigned>(nblk) : nullptr;
     L.gbelow = boxes ? a.take<unsigned long long>(nblk) : nullptr;
-    L.origin = a.take<float>(4);
+    L.origin = a.take<double>(4 * kSvOriginBlocks);
     L.qc = a.take<float4>(T);
     L.krec = a.take<float4>((size_t)Tpad * (d == 2 ? 1 : 2));
     L.part = a.take<float>((size_t)2 * d * splits * nqb * 256 * kSvR);
@@ -1447,7 +1462,7 @@ ct_status svgd_flow(const float* x, int T, int d, const float* score, float h, f
         }
     }
     const int Tpad = pad_keys(T);
-    hipLaunchKernelGGL(k_sv_origin, dim3(1), dim3(1024), 0, st, x, T, d, L.origin);
+    hipLaunchKernelGGL(k_sv_origin, dim3(kSvOriginBlocks), dim3(256), 0, st, x, T, d, L.origin);
     CT_CHECK_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_svgd_stage, dim3((Tpad + 255) / 256), dim3(256), 0, st, x, score, T, Tpad,
                        d, h > 0.f ? h : 0.f, L.st, L.origin, L.qc, L.krec);
