@@ -807,7 +807,7 @@ __global__ __launch_bounds__(1024) void k_med_list_scan(unsigned* __restrict__ c
 // next pair's rows and columns read while this one is evaluated.  The list is
 // dealt to the waves in turn (every pair of groups costs about the same); a
 // wave reads its list entries 64 at a time, one per lane.  Runs with
-// kBracketBlocks blocks: wave w = 4 blocks + wave owns candidate segment w and
+// kBracketBlocks blocks: wave w = 4 * blockIdx.x + wave owns candidate segment w and
 // writes its count to C.segcnt[w].
 template <int D>
 __global__ __launch_bounds__(256) void k_med_bracket(const float4* __restrict__ cs,
