@@ -267,3 +267,23 @@ def test_static_scratch_entry_rejects_before_launch():
     assert L.ct_sinkhorn_workspace_size(4096, 16384, ctypes.byref(ok)) > 64 << 20
     assert call(4096, 16384, ok) == _lib.CT_E_WORKSPACE
     assert b"static scratch" in L.ct_last_error()
+
+
+def test_svgd_workspace_grows_as_the_header_states():
+    """ct_svgd_workspace_size as include/ct.h describes it: the bracket's sample and
+    candidate buffers appear at T = 11000 (4 MiB + 4 bytes per 125 pairs), the
+    group boxes' buffers at T = 24576 (another 8 bytes per 125 pairs and 4 bytes per
+    pair of 64-point groups); d = 2 and 3 agree up to O(T)."""
+    from paper_2511_11514_amd import _lib
+    L = _lib.lib()
+    pairs = lambda T: T * (T - 1) // 2
+    for d in (2, 3):
+        ws = lambda T: L.ct_svgd_workspace_size(T, d)
+        assert ws(10999) < ws(11000)
+        assert ws(11000) - ws(10999) >= (1 << 22) + 4 * (pairs(11000) // 125) * 0.99
+        assert ws(24576) - ws(24575) >= 8 * (pairs(24576) // 125) * 0.99
+        ng = (24576 + 63) // 64
+        assert ws(24576) - ws(24575) >= 4 * ng * (ng + 1) // 2
+        assert 200e6 < ws(65536) < 300e6 and 400e6 < ws(92681) < 500e6
+        # above the median's limit (only a given bandwidth is accepted) the bracket's buffers go
+        assert ws(92682) < ws(92681) / 10
